@@ -1,0 +1,203 @@
+/*
+ * dualip.h - C ABI of the MI355X (gfx950) ridge-regularized matching-LP dual
+ * ascent library.
+ *
+ * Problem (paper eq. 1):  min_{x in C} c^T x + (gamma/2)||x||^2  s.t.  A x <= b
+ *   x        one variable per eligible (user i, item j) pair, user-major
+ *   C        product of per-user sets: simplex {x_i >= 0, sum x_i <= z},
+ *            simplex {x_i >= 0, sum x_i = z}, or box [0,u]^(d_i) (Section 3.3)
+ *   A        m coupling families; family k has one row per item j and
+ *            A[(k,j),(i,j)] = a_kij (Definition 1: diagonal per-user blocks)
+ * Dual (eq. 2): g(lam) = min_{x in C} c^T x + (gamma/2)||x||^2 + lam^T (A x - b)
+ * Primal recovery (eq. 3): x*(lam) = Pi_C(-(A^T lam + c)/gamma)
+ * Gradient (eq. 4): grad g(lam) = A x*(lam) - b
+ *
+ * The three calls mirror the paper's programming model (Table 1):
+ *   ObjectiveFunction.calculate -> dl_dual_grad
+ *   ProjectionMap               -> dl_project
+ *   Maximizer                   -> dl_solve (and the stepwise dl_solver_*)
+ *
+ * Conventions shared by every entry point
+ *   Memory    Arrays marked "device" are caller-owned device pointers on the
+ *             problem's device; arrays marked "host" are host memory.  The
+ *             library never frees caller memory.  dl_problem_create copies
+ *             what it needs, so the caller may free its inputs when it returns.
+ *   Streams   Every call is ordered on the stream given at create time
+ *             (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream;
+ *             NULL = the default stream).  Calls that return host values
+ *             synchronise that stream; the others only enqueue work.
+ *   Errors    Every call returns a dl_status; on failure dl_last_error()
+ *             gives a message (thread-local).  Nothing aborts or throws across
+ *             the ABI.  Positive statuses are non-fatal.
+ *   Units     lam, grad and A x are in the problem's own units even when
+ *             Jacobi scaling is on (the scaling is internal to the solver).
+ *   Threads   A dl_problem or dl_solver must not be used from two threads at
+ *             once; distinct objects are independent.
+ */
+#ifndef DUALIP_H
+#define DUALIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DL_OK = 0,
+  DL_NOT_CONVERGED = 1, /* solve stopped at its iteration cap; results valid */
+  DL_EINVAL = -1,       /* invalid argument or invalid instance data */
+  DL_ENOMEM = -2,       /* device or host allocation failed */
+  DL_EHIP = -3,         /* a HIP runtime call failed */
+  DL_EUNSUPPORTED = -4, /* valid but outside what this build supports */
+  DL_DIVERGED = -5,     /* a non-finite value appeared in the dual iterate */
+  DL_NUMERIC = -6       /* a non-finite dual objective or certificate */
+} dl_status;
+
+/* Per-user simple set (Section 3.3). radius is z for the simplices, u for the box. */
+typedef enum { DL_PROJ_SIMPLEX_LE = 0, DL_PROJ_SIMPLEX_EQ = 1, DL_PROJ_BOX = 2 } dl_proj_kind;
+
+/* Storage of c and a in device memory. DL_BF16 rounds (to nearest even) at
+ * create time; projection and accumulation stay FP32 / fixed point, the dual
+ * objective and gap FP64. */
+typedef enum { DL_F32 = 0, DL_BF16 = 1 } dl_storage;
+
+typedef struct dl_problem dl_problem;
+typedef struct dl_solver dl_solver;
+
+typedef struct {
+  int64_t n_users;          /* I >= 0 */
+  int32_t n_items;          /* J >= 1 */
+  int32_t n_families;       /* m, 1..4 */
+  const int64_t* row_ptr;   /* device, I+1: row_ptr[0] = 0, nondecreasing */
+  const int32_t* item_idx;  /* device, nnz: strictly increasing within each row, in [0, J) */
+  const float* c;           /* device, nnz: linear cost c_ij (finite) */
+  const float* a;           /* device, m*nnz family-major (finite), or NULL: every a_kij = 1 */
+  const double* b;          /* host, m*J, family-major right-hand side */
+  int32_t proj;             /* dl_proj_kind */
+  int32_t storage;          /* dl_storage */
+  double radius;            /* z (simplex) or u (box), > 0 */
+  int32_t jacobi;           /* 1: Jacobi row scaling in the solver (Appendix C) */
+  int32_t wg_per_cu;        /* gradient-pass workgroups per compute unit, 0 = default */
+  void* stream;             /* hipStream_t */
+} dl_problem_desc;
+
+/* Facts about a created problem (all host values). */
+typedef struct {
+  int64_t n_users, nnz;
+  int32_t n_items, n_families;
+  int32_t n_stored_families;  /* families whose a is not identically 1 */
+  int32_t n_workgroups;       /* gradient-pass grid */
+  int64_t n_tasks;            /* wavefront tasks per pass */
+  double lhat;                /* bound on ||A'||_2^2, A' = DA (exact for m = 1) */
+  double bytes_per_pass;      /* algorithmic HBM bytes of one gradient pass */
+  double device_bytes;        /* library-owned device memory */
+  int32_t max_degree;
+  int32_t n_buckets;
+  int32_t bucket_glog[8];     /* log2 lanes per user of each degree bucket (7 = long rows) */
+  int64_t bucket_users[8];
+  float qscale[4];            /* fixed-point step of each family's accumulation is 1/qscale */
+} dl_problem_info;
+
+/*
+ * Creates a problem: validates the CSR instance, reorders users by degree,
+ * builds the per-wavefront task table, computes the Jacobi scaling D and the
+ * step bound lhat (Appendix C), and copies c and a into library storage.
+ * Returns DL_EINVAL for malformed data (non-monotone row_ptr, item out of
+ * range or repeated in a row, non-finite c/a/b, radius <= 0), DL_EUNSUPPORTED
+ * when m*J exceeds the on-chip accumulation capacity (13,000), DL_ENOMEM or
+ * DL_EHIP otherwise.  Synchronises the stream before returning.
+ */
+dl_status dl_problem_create(const dl_problem_desc* desc, dl_problem** out);
+
+/* Frees everything the problem owns. NULL-safe. */
+void dl_problem_destroy(dl_problem* prob);
+
+dl_status dl_problem_get_info(const dl_problem* prob, dl_problem_info* out);
+
+/*
+ * ObjectiveFunction.calculate (Table 1; eqs. 2-4) at lam, gamma > 0.
+ *   lambda    device, m*J: the dual point (used at FP32 in the per-nnz gather)
+ *   grad      device, m*J, nullable: A x*(lam) - b
+ *   dual_obj  host, nullable: g(lam) in FP64 (synchronises)
+ *   x         device, nnz, nullable: x*(lam) in the caller's CSR order
+ */
+dl_status dl_dual_grad(dl_problem* prob, const double* lambda, double gamma, double* grad,
+                       double* dual_obj, float* x);
+
+/*
+ * ProjectionMap (Table 1): x = Pi_C(v) row by row, v and x device arrays of
+ * length nnz in the caller's CSR order (v and x may alias).
+ */
+dl_status dl_project(dl_problem* prob, const float* v, float* x);
+
+/* ----------------------------------------------------------------------- */
+/* Maximizer: accelerated projected dual ascent with gamma continuation     */
+/* (Sections 4.4 and 6, Appendix C).                                        */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_stages;        /* >= 1 */
+  int32_t check_every;     /* certificate period in the final stage; 0 = only at the end */
+  const double* gammas;    /* host, n_stages, each > 0 */
+  const int64_t* iters;    /* host, n_stages; the last may be -1: until tol or max_iters */
+  double tol;              /* stop when the certified relative gap <= tol (final stage) */
+  int64_t max_iters;       /* total iteration cap */
+  int32_t reset_momentum;  /* 1: restart the momentum at each stage switch */
+  int32_t pad0;
+  double step_scale;       /* step = step_scale * gamma / lhat */
+} dl_solve_opts;
+
+typedef struct {
+  int64_t iters;           /* iterations run */
+  int32_t stage;           /* stage index at exit */
+  int32_t status;          /* dl_status of the solve */
+  double gamma;            /* gamma of the last stage run */
+  double dual_obj;         /* g_gamma(lam) */
+  double primal_obj;       /* P_gamma(x~) of the feasible repair of x*(lam) */
+  double rel_gap;          /* (P_gamma(x~) - g_gamma(lam)) / max(1, |g_gamma(lam)|) */
+  double max_slack;        /* max (A x*(lam) - b)^+ */
+  double lagr_gap;         /* -lam^T grad g(lam) */
+  int64_t n_checks;        /* certificates evaluated */
+  double wall_ms;          /* host wall time of the call */
+} dl_solve_stats;
+
+/*
+ * Runs the whole schedule from lambda0 (device, m*J, nullable = 0) and writes
+ * the final lam (device, m*J) and stats (host).  The certificate (two extra
+ * gradient passes) is evaluated every check_every iterations of the final
+ * stage and at the end.  Returns DL_OK, DL_NOT_CONVERGED (cap reached, results
+ * valid), DL_DIVERGED (non-finite iterate) or an error.
+ */
+dl_status dl_solve(dl_problem* prob, const dl_solve_opts* opts, const double* lambda0,
+                   double* lambda_out, dl_solve_stats* stats);
+
+/* Stepwise access to the same iteration, for trajectories and timing. */
+dl_status dl_solver_create(dl_problem* prob, const double* lambda0, dl_solver** out);
+void dl_solver_destroy(dl_solver* s);
+/* Starts a stage at gamma with step step_scale*gamma/lhat; reset=1 restarts the momentum. */
+dl_status dl_solver_set_stage(dl_solver* s, double gamma, double step_scale, int32_t reset);
+/* Enqueues n accelerated iterations (gradient pass + fused update each). No sync. */
+dl_status dl_solver_step(dl_solver* s, int64_t n);
+/* Current lam (device, m*J). */
+dl_status dl_solver_get_lambda(dl_solver* s, double* lambda_out);
+/* Certificate at the current lam and gamma (synchronises). */
+dl_status dl_solver_certificate(dl_solver* s, dl_solve_stats* out);
+
+typedef struct {
+  int64_t n_grad;          /* timed gradient passes */
+  double grad_ms_total;    /* summed HIP-event durations of those passes */
+  int64_t n_update;
+  double update_ms_total;
+} dl_timing;
+/* Brackets every later gradient pass and update with HIP events on the stream. */
+dl_status dl_solver_enable_timing(dl_solver* s, int32_t on);
+/* Synchronises and returns the sums since timing was enabled. */
+dl_status dl_solver_get_timing(dl_solver* s, dl_timing* out);
+
+/* Message for the last non-OK status on this thread. */
+const char* dl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DUALIP_H */

@@ -1,0 +1,320 @@
+"""Python binding of libdualip (gfx950 ridge-regularized matching-LP dual ascent).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library declared in include/dualip.h.  PyTorch supplies device memory and the
+stream.  The binding raises if the built library is missing; there is no CPU
+fallback.
+
+Function names follow the C ABI (dl_problem_create, dl_dual_grad, dl_project,
+dl_solve, dl_solver_*); the classes Problem and Solver wrap them for tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdualip.so")
+
+DL_OK, DL_NOT_CONVERGED = 0, 1
+STATUS = {0: "DL_OK", 1: "DL_NOT_CONVERGED", -1: "DL_EINVAL", -2: "DL_ENOMEM", -3: "DL_EHIP",
+          -4: "DL_EUNSUPPORTED", -5: "DL_DIVERGED", -6: "DL_NUMERIC"}
+PROJ = {"simplex_le": 0, "simplex_eq": 1, "box": 2}
+STORAGE = {"f32": 0, "bf16": 1}
+
+
+class DualipError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dl_problem_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_users", ctypes.c_int64),
+        ("n_items", ctypes.c_int32),
+        ("n_families", ctypes.c_int32),
+        ("row_ptr", ctypes.c_void_p),
+        ("item_idx", ctypes.c_void_p),
+        ("c", ctypes.c_void_p),
+        ("a", ctypes.c_void_p),
+        ("b", ctypes.c_void_p),
+        ("proj", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("radius", ctypes.c_double),
+        ("jacobi", ctypes.c_int32),
+        ("wg_per_cu", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class dl_problem_info(ctypes.Structure):
+    _fields_ = [
+        ("n_users", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("n_items", ctypes.c_int32),
+        ("n_families", ctypes.c_int32),
+        ("n_stored_families", ctypes.c_int32),
+        ("n_workgroups", ctypes.c_int32),
+        ("n_tasks", ctypes.c_int64),
+        ("lhat", ctypes.c_double),
+        ("bytes_per_pass", ctypes.c_double),
+        ("device_bytes", ctypes.c_double),
+        ("max_degree", ctypes.c_int32),
+        ("n_buckets", ctypes.c_int32),
+        ("bucket_glog", ctypes.c_int32 * 8),
+        ("bucket_users", ctypes.c_int64 * 8),
+        ("qscale", ctypes.c_float * 4),
+    ]
+
+
+class dl_solve_opts(ctypes.Structure):
+    _fields_ = [
+        ("n_stages", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("gammas", ctypes.c_void_p),
+        ("iters", ctypes.c_void_p),
+        ("tol", ctypes.c_double),
+        ("max_iters", ctypes.c_int64),
+        ("reset_momentum", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("step_scale", ctypes.c_double),
+    ]
+
+
+class dl_solve_stats(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int64),
+        ("stage", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("dual_obj", ctypes.c_double),
+        ("primal_obj", ctypes.c_double),
+        ("rel_gap", ctypes.c_double),
+        ("max_slack", ctypes.c_double),
+        ("lagr_gap", ctypes.c_double),
+        ("n_checks", ctypes.c_int64),
+        ("wall_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class dl_timing(ctypes.Structure):
+    _fields_ = [
+        ("n_grad", ctypes.c_int64),
+        ("grad_ms_total", ctypes.c_double),
+        ("n_update", ctypes.c_int64),
+        ("update_ms_total", ctypes.c_double),
+    ]
+
+
+# Every symbol include/dualip.h declares, with its ctypes signature.
+_VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+SIGNATURES = {
+    "dl_problem_create": ([ctypes.POINTER(dl_problem_desc), ctypes.POINTER(_VP)], _I32),
+    "dl_problem_destroy": ([_VP], None),
+    "dl_problem_get_info": ([_VP, ctypes.POINTER(dl_problem_info)], _I32),
+    "dl_dual_grad": ([_VP, _VP, _D, _VP, _VP, _VP], _I32),
+    "dl_project": ([_VP, _VP, _VP], _I32),
+    "dl_solve": ([_VP, ctypes.POINTER(dl_solve_opts), _VP, _VP, ctypes.POINTER(dl_solve_stats)], _I32),
+    "dl_solver_create": ([_VP, _VP, ctypes.POINTER(_VP)], _I32),
+    "dl_solver_destroy": ([_VP], None),
+    "dl_solver_set_stage": ([_VP, _D, _D, _I32], _I32),
+    "dl_solver_step": ([_VP, _I64], _I32),
+    "dl_solver_get_lambda": ([_VP, _VP], _I32),
+    "dl_solver_certificate": ([_VP, ctypes.POINTER(dl_solve_stats)], _I32),
+    "dl_solver_enable_timing": ([_VP, _I32], _I32),
+    "dl_solver_get_timing": ([_VP, ctypes.POINTER(dl_timing)], _I32),
+    "dl_last_error": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads the built library (raises if it is missing: no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"libdualip.so is not built ({path}); run paper_2606_07777_amd/build.py")
+        lib = ctypes.CDLL(path)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, allow=(DL_OK,)) -> int:
+    if status not in allow and status < 0:
+        raise DualipError(status, load().dl_last_error().decode())
+    return status
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(torch, stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Problem:
+    """A created dl_problem on the current device.
+
+    row_ptr (int64), item_idx (int32), c (float32) and a (float32, m x nnz, or
+    None) may be torch tensors on the device or numpy arrays (copied there);
+    b is host data (m x J).
+    """
+
+    def __init__(self, n_users, n_items, n_families, row_ptr, item_idx, c, a, b, proj="simplex_le",
+                 radius=1.0, storage="f32", jacobi=True, wg_per_cu=0, stream=None):
+        import torch
+        self.torch = torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def dev_t(x, dt):
+            if x is None:
+                return None
+            if isinstance(x, torch.Tensor):
+                return x.to(device=dev, dtype=dt).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(x)).to(device=dev, dtype=dt)
+
+        self.m, self.J, self.I = int(n_families), int(n_items), int(n_users)
+        self._rp = dev_t(row_ptr, torch.int64)
+        self._idx = dev_t(item_idx, torch.int32)
+        self._c = dev_t(c, torch.float32)
+        self._a = dev_t(a, torch.float32)
+        bh = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+        self.stream = _stream(torch, stream)
+        desc = dl_problem_desc(self.I, self.J, self.m, _ptr(self._rp), _ptr(self._idx), _ptr(self._c),
+                               _ptr(self._a), bh.ctypes.data, PROJ[proj], STORAGE[storage], float(radius),
+                               int(jacobi), int(wg_per_cu), self.stream)
+        h = ctypes.c_void_p()
+        _check(load().dl_problem_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        # the library copied what it needs
+        self._rp = self._idx = self._c = self._a = None
+        self.nnz = self.info()["nnz"]
+
+    @classmethod
+    def from_instance(cls, inst, storage="f32", jacobi=True, wg_per_cu=0, stream=None):
+        """From any object with the attributes of a CSR matching instance."""
+        return cls(inst.n_users, inst.n_items, inst.n_families, inst.row_ptr, inst.item_idx, inst.c, inst.a,
+                   inst.b, inst.proj, inst.radius, storage, jacobi, wg_per_cu, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dl_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        o = dl_problem_info()
+        _check(load().dl_problem_get_info(self.handle, ctypes.byref(o)))
+        d = {f: getattr(o, f) for f, _ in o._fields_}
+        nb = d["n_buckets"]
+        d["bucket_glog"] = list(o.bucket_glog)[:nb]
+        d["bucket_users"] = list(o.bucket_users)[:nb]
+        d["qscale"] = list(o.qscale)[:self.m]
+        return d
+
+    def _empty(self, n, dt):
+        return self.torch.empty(n, dtype=dt, device="cuda")
+
+    def dual_grad(self, lam, gamma: float, want_obj=True, want_x=False):
+        """dl_dual_grad: (g(lam) or None, grad tensor [m*J] f64, x tensor [nnz] f32 or None)."""
+        torch = self.torch
+        lam = lam.to(device="cuda", dtype=torch.float64).contiguous()
+        grad = self._empty(self.m * self.J, torch.float64)
+        x = self._empty(self.nnz, torch.float32) if want_x else None
+        g = ctypes.c_double()
+        _check(load().dl_dual_grad(self.handle, _ptr(lam), float(gamma), _ptr(grad),
+                                   ctypes.addressof(g) if want_obj else None, _ptr(x)))
+        torch.cuda.current_stream().synchronize()
+        return (g.value if want_obj else None), grad, x
+
+    def project(self, v):
+        """dl_project: x = Pi_C(v) row by row (caller order)."""
+        torch = self.torch
+        v = v.to(device="cuda", dtype=torch.float32).contiguous()
+        x = self._empty(self.nnz, torch.float32)
+        _check(load().dl_project(self.handle, _ptr(v), _ptr(x)))
+        return x
+
+    def solve(self, gammas: Sequence[float], iters: Sequence[int], tol=1e-4, max_iters=20000, check_every=10,
+              reset_momentum=True, step_scale=1.0, lam0=None):
+        """dl_solve over the schedule; returns (lam tensor f64 [m*J], stats dict)."""
+        torch = self.torch
+        g = np.ascontiguousarray(gammas, dtype=np.float64)
+        it = np.ascontiguousarray(iters, dtype=np.int64)
+        o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
+                          int(reset_momentum), 0, float(step_scale))
+        l0 = None if lam0 is None else lam0.to(device="cuda", dtype=torch.float64).contiguous()
+        out = self._empty(self.m * self.J, torch.float64)
+        st = dl_solve_stats()
+        _check(load().dl_solve(self.handle, ctypes.byref(o), _ptr(l0), _ptr(out), ctypes.byref(st)),
+               allow=(DL_OK, DL_NOT_CONVERGED))
+        return out, st.as_dict()
+
+    def solver(self, lam0=None) -> "Solver":
+        return Solver(self, lam0)
+
+
+class Solver:
+    """Stepwise Maximizer (dl_solver_*)."""
+
+    def __init__(self, prob: Problem, lam0=None):
+        self.prob = prob
+        torch = prob.torch
+        self._l0 = None if lam0 is None else lam0.to(device="cuda", dtype=torch.float64).contiguous()
+        h = ctypes.c_void_p()
+        _check(load().dl_solver_create(prob.handle, _ptr(self._l0), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dl_solver_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stage(self, gamma: float, step_scale: float = 1.0, reset: bool = True):
+        _check(load().dl_solver_set_stage(self.handle, float(gamma), float(step_scale), int(reset)))
+
+    def step(self, n: int):
+        _check(load().dl_solver_step(self.handle, int(n)))
+
+    def lam(self):
+        out = self.prob._empty(self.prob.m * self.prob.J, self.prob.torch.float64)
+        _check(load().dl_solver_get_lambda(self.handle, _ptr(out)))
+        return out
+
+    def certificate(self) -> dict:
+        st = dl_solve_stats()
+        _check(load().dl_solver_certificate(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def enable_timing(self, on: bool = True):
+        _check(load().dl_solver_enable_timing(self.handle, int(on)))
+
+    def timing(self) -> dict:
+        t = dl_timing()
+        _check(load().dl_solver_get_timing(self.handle, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in t._fields_}

@@ -1,0 +1,157 @@
+// Internal declarations of the gfx950 dual-ascent library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "dualip.h"
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void dl_set_error(const std::string& msg);
+
+#define DL_HIP_TRY(expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      dl_set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                \
+      return (e_ == hipErrorOutOfMemory) ? DL_ENOMEM : DL_EHIP;                       \
+    }                                                                                 \
+  } while (0)
+
+#define DL_CHECK_ARG(cond, msg)   \
+  do {                            \
+    if (!(cond)) {                \
+      dl_set_error(msg);          \
+      return DL_EINVAL;           \
+    }                             \
+  } while (0)
+
+#define DL_TRY(expr)              \
+  do {                            \
+    dl_status s_ = (expr);        \
+    if (s_ < 0) return s_;        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Layout constants
+// ---------------------------------------------------------------------------
+constexpr int DL_WG = 1024;              // gradient-pass workgroup size (16 wavefronts)
+constexpr int DL_WAVES = DL_WG / 64;
+constexpr int DL_MAX_BUCKETS = 8;
+constexpr int DL_LONG = 7;               // bucket code of rows longer than 64*KMAX
+constexpr int DL_MAX_MJ = 13000;         // m*J that fits the LDS accumulation (12 B per entry)
+constexpr int DL_MAX_FAMILIES = 4;
+
+// A degree bucket: users [user_begin, user_end) of the reordered problem (sorted
+// by degree, longest first) served by groups of 2^glog lanes, 64/2^glog users
+// per wavefront task; glog == DL_LONG serves one user per task with a
+// wavefront-wide loop over the row.
+struct dl_bucket {
+  int64_t task_begin;
+  int64_t user_begin;
+  int64_t user_end;
+  int32_t glog;
+  int32_t pad;
+};
+
+enum : int {
+  M_HIST = 1,    // accumulate A x into the per-workgroup fixed-point histogram
+  M_OBJ = 2,     // accumulate the per-user Lagrangian terms (FP64 per workgroup)
+  M_REPAIR = 4,  // accumulate c.x~ + gamma/2 x~^2 with x~ = r_j x (certificate)
+  M_VIN = 8,     // v given in caller order (ProjectionMap), no gather
+};
+
+struct dl_grad_args {
+  // reordered instance
+  const int64_t* rp;       // I_new + 1
+  const int32_t* idx;      // nnz
+  const void* cval;        // nnz, float or bf16
+  const void* aval;        // n_stored * nnz
+  const int64_t* orig_rp;  // per reordered user: row start in the caller's order
+  int64_t nnz;
+  int32_t J, m;
+  int32_t a_slot[DL_MAX_FAMILIES];  // stored slot of family k, -1: a == 1
+  float qscale[DL_MAX_FAMILIES];    // fixed-point scale of family k
+  // tasks
+  const int64_t* wg_task;           // n_wg + 1
+  int32_t n_buckets;
+  int32_t proj;                     // dl_proj_kind
+  dl_bucket bk[DL_MAX_BUCKETS];
+  float radius;
+  // iteration inputs
+  float neg_inv_gamma;
+  float gamma;
+  float pad0;
+  const float* mu;                  // m*J, lam in problem units (FP32)
+  const float* rfac;                // J, repair factor (M_REPAIR)
+  const float* v_in;                // nnz caller order (M_VIN)
+  // outputs
+  unsigned long long* part;         // n_wg * m*J
+  double* obj_part;                 // n_wg
+  float* x_out;                     // nnz caller order, nullable
+};
+
+struct dl_problem {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t I = 0, I_active = 0, nnz = 0;
+  int32_t J = 0, m = 0, proj = 0, storage = 0, jacobi = 0;
+  double radius = 1.0;
+  int kmax = 16;
+  int mf = 1;            // compiled family bound of the kernel variant (1 or 4)
+  bool has_a = false;    // at least one stored family
+  int n_stored = 0;
+  int a_slot[DL_MAX_FAMILIES] = {-1, -1, -1, -1};
+  float qscale[DL_MAX_FAMILIES] = {0, 0, 0, 0};
+  int32_t max_degree = 0;
+
+  // reordered device layout
+  int64_t* rp = nullptr;
+  int32_t* idx = nullptr;
+  void* cval = nullptr;
+  void* aval = nullptr;
+  int64_t* orig_rp = nullptr;
+
+  // task table
+  std::vector<dl_bucket> buckets;
+  int64_t n_tasks = 0;
+  int n_wg = 0;
+  int64_t* wg_task = nullptr;
+
+  // item space (device)
+  double* b = nullptr;       // m*J
+  double* D = nullptr;       // m*J Jacobi scaling (1 without Jacobi)
+  double lhat = 1.0;
+  std::vector<double> b_host, D_host;
+
+  // per-pass scratch (device)
+  unsigned long long* part = nullptr;  // n_wg * m*J
+  double* obj_part = nullptr;          // n_wg
+  double* pobj_part = nullptr;         // n_wg
+  float* mu = nullptr;                 // m*J
+  float* rfac = nullptr;               // J
+  double* lam_tmp = nullptr;           // m*J
+  double* cert_out = nullptr;          // 8 doubles
+  double* cert_host = nullptr;         // pinned, 8 doubles
+  double device_bytes = 0;
+};
+
+// Gradient pass and projection launches (dl_grad.hip).
+dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double gamma,
+                         const float* rfac, const float* v_in, float* x_out, double* obj_part);
+size_t dl_grad_lds_bytes(const dl_problem* P, int mode);
+dl_status dl_grad_prepare(const dl_problem* P);
+
+// BF16 helpers (storage form: c and a in bfloat16, FP32 arithmetic).
+__host__ __device__ inline uint16_t dl_f32_to_bf16_rne(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}

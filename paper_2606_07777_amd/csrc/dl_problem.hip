@@ -1,0 +1,467 @@
+// Problem creation: validation, degree reordering, task table, item statistics,
+// Jacobi scaling and the step bound (Appendix C), storage conversion.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "dl_common.h"
+
+static thread_local std::string g_last_error;
+
+void dl_set_error(const std::string& msg) { g_last_error = msg; }
+
+extern "C" const char* dl_last_error(void) { return g_last_error.c_str(); }
+
+namespace {
+
+enum : int { F_RANGE = 1, F_ORDER = 2, F_CNAN = 4, F_ANAN = 8 };
+
+// One thread per row of the caller's CSR: item range, strictly increasing
+// items, finite values; per-family max |a| and whether a family is all ones.
+__global__ void validate_rows(const int64_t* rp, const int32_t* idx, const float* c, const float* a, int64_t I,
+                              int32_t J, int32_t m, int64_t nnz, int* flags, unsigned* amax_bits,
+                              int* non_unit) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= I) return;
+  int64_t s = rp[i], e = rp[i + 1];
+  int bad = 0;
+  int32_t prev = -1;
+  for (int64_t k = s; k < e; ++k) {
+    int32_t j = idx[k];
+    if (j < 0 || j >= J) bad |= F_RANGE;
+    if (j <= prev) bad |= F_ORDER;
+    prev = j;
+    if (!isfinite(c[k])) bad |= F_CNAN;
+  }
+  if (a) {
+    for (int f = 0; f < m; ++f) {
+      float mx = 0.f;
+      int nu = 0;
+      for (int64_t k = s; k < e; ++k) {
+        float v = a[(int64_t)f * nnz + k];
+        if (!isfinite(v)) bad |= F_ANAN;
+        mx = fmaxf(mx, fabsf(v));
+        nu |= (v != 1.0f);
+      }
+      if (mx > 0.f) atomicMax(amax_bits + f, __float_as_uint(mx));
+      if (nu) atomicOr(non_unit + f, 1);
+    }
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+// One wavefront per reordered user: copy its row from the caller's CSR.
+__global__ void gather_rows(const int64_t* orig_rp, const int64_t* new_rp, int64_t I, const int32_t* idx_in,
+                            const float* c_in, const float* a_in, int64_t nnz, int n_stored, const int* fam_of_slot,
+                            int bf16, int32_t* idx_out, void* c_out, void* a_out) {
+  int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (u >= I) return;
+  int64_t os = orig_rp[u], ns = new_rp[u];
+  int64_t d = new_rp[u + 1] - ns;
+  for (int64_t e = lane; e < d; e += 64) {
+    idx_out[ns + e] = idx_in[os + e];
+    float cv = c_in[os + e];
+    if (bf16) reinterpret_cast<uint16_t*>(c_out)[ns + e] = dl_f32_to_bf16_rne(cv);
+    else reinterpret_cast<float*>(c_out)[ns + e] = cv;
+    for (int sl = 0; sl < n_stored; ++sl) {
+      float av = a_in[(int64_t)fam_of_slot[sl] * nnz + os + e];
+      int64_t dst = (int64_t)sl * nnz + ns + e;
+      if (bf16) reinterpret_cast<uint16_t*>(a_out)[dst] = dl_f32_to_bf16_rne(av);
+      else reinterpret_cast<float*>(a_out)[dst] = av;
+    }
+  }
+}
+
+// Item statistics over the stored layout, as exact integer sums:
+//   cnt[j]                       number of users eligible for item j
+//   M[(j*m + k)*m + l], k <= l   sum_i a_kij a_lij, on a 2^-E_kl fixed-point grid
+// Values are those the kernels will read (after any BF16 rounding).
+template <typename TV>
+__device__ inline float ld(const void* p, int64_t e);
+template <>
+__device__ inline float ld<float>(const void* p, int64_t e) { return reinterpret_cast<const float*>(p)[e]; }
+template <>
+__device__ inline float ld<uint16_t>(const void* p, int64_t e) {
+  return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(p)[e] << 16);
+}
+
+template <typename TV>
+__global__ void item_stats(const int32_t* idx, const void* aval, int64_t nnz, int32_t J, int32_t m,
+                           const int* slot, const double* escale, unsigned long long* cnt,
+                           unsigned long long* M) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = idx[e];
+    atomicAdd(cnt + j, 1ull);
+    for (int k = 0; k < m; ++k) {
+      double ak = slot[k] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[k] * nnz + e) : 1.0;
+      for (int l = k; l < m; ++l) {
+        if (slot[k] < 0 && slot[l] < 0) continue;  // 1*1: equals cnt
+        double al = slot[l] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[l] * nnz + e) : 1.0;
+        long long q = __double2ll_rn(ak * al * escale[k * m + l]);
+        atomicAdd(M + ((int64_t)j * m + k) * m + l, (unsigned long long)q);
+      }
+    }
+  }
+}
+
+template <typename T>
+dl_status dmalloc(dl_problem* P, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  DL_HIP_TRY(hipMalloc((void**)p, n * sizeof(T)));
+  P->device_bytes += (double)(n * sizeof(T));
+  return DL_OK;
+}
+
+void free_problem(dl_problem* P) {
+  if (!P) return;
+  void* ptrs[] = {P->rp, P->idx, P->cval, P->aval, P->orig_rp, P->wg_task, P->b, P->D, P->part,
+                  P->obj_part, P->pobj_part, P->mu, P->rfac, P->lam_tmp, P->cert_out};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  if (P->cert_host) (void)hipHostFree(P->cert_host);
+  delete P;
+}
+
+dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
+  const int64_t I = d->n_users;
+  const int32_t J = d->n_items, m = d->n_families;
+  P->I = I;
+  P->J = J;
+  P->m = m;
+  P->proj = d->proj;
+  P->storage = d->storage;
+  P->radius = d->radius;
+  P->jacobi = d->jacobi ? 1 : 0;
+  P->stream = (hipStream_t)d->stream;
+  DL_HIP_TRY(hipGetDevice(&P->device));
+  hipStream_t st = P->stream;
+
+  // ---- row pointers on the host: validation, degree order, tasks ----
+  std::vector<int64_t> rp((size_t)I + 1);
+  DL_HIP_TRY(hipMemcpyAsync(rp.data(), d->row_ptr, sizeof(int64_t) * (size_t)(I + 1), hipMemcpyDeviceToHost, st));
+  DL_HIP_TRY(hipStreamSynchronize(st));
+  DL_CHECK_ARG(rp[0] == 0, "row_ptr[0] must be 0");
+  int64_t maxdeg = 0;
+  for (int64_t i = 0; i < I; ++i) {
+    int64_t dg = rp[i + 1] - rp[i];
+    DL_CHECK_ARG(dg >= 0, "row_ptr must be nondecreasing");
+    DL_CHECK_ARG(dg <= J, "a row has more entries than there are items");
+    maxdeg = std::max(maxdeg, dg);
+  }
+  const int64_t nnz = rp[I];
+  DL_CHECK_ARG(nnz == 0 || (d->item_idx && d->c), "item_idx and c are required");
+  P->nnz = nnz;
+  P->max_degree = (int32_t)maxdeg;
+
+  // stable counting sort of users by degree, longest first
+  std::vector<int64_t> count((size_t)maxdeg + 2, 0);
+  for (int64_t i = 0; i < I; ++i) count[(size_t)(maxdeg - (rp[i + 1] - rp[i]))]++;
+  std::vector<int64_t> pos((size_t)maxdeg + 2, 0);
+  for (int64_t k = 1; k <= maxdeg + 1; ++k) pos[k] = pos[k - 1] + count[k - 1];
+  std::vector<int64_t> perm((size_t)I);
+  for (int64_t i = 0; i < I; ++i) perm[(size_t)pos[(size_t)(maxdeg - (rp[i + 1] - rp[i]))]++] = i;
+  std::vector<int64_t> new_rp((size_t)I + 1), orig_rp((size_t)std::max<int64_t>(I, 1));
+  new_rp[0] = 0;
+  int64_t I_active = 0;
+  for (int64_t u = 0; u < I; ++u) {
+    int64_t old = perm[(size_t)u];
+    int64_t dg = rp[old + 1] - rp[old];
+    new_rp[u + 1] = new_rp[u] + dg;
+    orig_rp[u] = rp[old];
+    if (dg > 0) I_active = u + 1;
+  }
+  P->I_active = I_active;
+
+  // degree buckets: 2^glog lanes per user, at most kmax elements per lane
+  P->mf = (m == 1) ? 1 : 4;
+  P->kmax = (m == 1) ? 16 : 8;
+  const int kmax = P->kmax;
+  auto code_of = [&](int64_t dg) -> int {
+    if (dg > 64 * (int64_t)kmax) return DL_LONG;
+    for (int gl = 0; gl <= 6; ++gl)
+      if (((dg + (1 << gl) - 1) >> gl) <= kmax) return gl;
+    return DL_LONG;
+  };
+  P->buckets.clear();
+  std::vector<double> task_cost;
+  int64_t u = 0;
+  while (u < I_active) {
+    int code = code_of(new_rp[u + 1] - new_rp[u]);
+    int64_t ue = u;
+    while (ue < I_active && code_of(new_rp[ue + 1] - new_rp[ue]) == code) ++ue;
+    dl_bucket B;
+    B.task_begin = (int64_t)task_cost.size();
+    B.user_begin = u;
+    B.user_end = ue;
+    B.glog = code;
+    B.pad = 0;
+    if ((int)P->buckets.size() >= DL_MAX_BUCKETS) {
+      dl_set_error("internal: too many degree buckets");
+      return DL_EUNSUPPORTED;
+    }
+    P->buckets.push_back(B);
+    if (code == DL_LONG) {
+      for (int64_t x = u; x < ue; ++x) task_cost.push_back(3.0 * (double)(new_rp[x + 1] - new_rp[x]) + 64.0);
+    } else {
+      const int64_t upt = 64 >> code;
+      for (int64_t x = u; x < ue; x += upt) {
+        int64_t d0 = new_rp[x + 1] - new_rp[x];
+        int64_t K = (d0 + (1 << code) - 1) >> code;
+        if (K > kmax) {
+          dl_set_error("internal: bucket bound violated");
+          return DL_EUNSUPPORTED;
+        }
+        task_cost.push_back(64.0 * (double)K + 64.0);
+      }
+    }
+    u = ue;
+  }
+  P->n_tasks = (int64_t)task_cost.size();
+
+  int n_cu = 0;
+  DL_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
+  const int wpc = d->wg_per_cu > 0 ? d->wg_per_cu : 1;
+  int64_t n_wg = std::min<int64_t>((int64_t)n_cu * wpc, (P->n_tasks + DL_WAVES - 1) / DL_WAVES);
+  if (P->n_tasks > 0 && n_wg < 1) n_wg = 1;
+  P->n_wg = (int)n_wg;
+  std::vector<int64_t> wg_task((size_t)n_wg + 1, 0);
+  {
+    double tot = 0.0;
+    for (double c : task_cost) tot += c;
+    double run = 0.0;
+    int64_t t = 0;
+    for (int64_t w = 1; w < n_wg; ++w) {
+      double target = tot * (double)w / (double)n_wg;
+      while (t < P->n_tasks && run + task_cost[(size_t)t] * 0.5 < target) run += task_cost[(size_t)t++];
+      wg_task[(size_t)w] = t;
+    }
+    wg_task[(size_t)n_wg] = P->n_tasks;
+  }
+
+  // ---- device validation of the caller's arrays ----
+  int* dflags = nullptr;
+  DL_HIP_TRY(hipMalloc((void**)&dflags, sizeof(int) * 16));
+  struct FreeGuard {
+    void* p;
+    ~FreeGuard() { if (p) (void)hipFree(p); }
+  } fg{dflags};
+  DL_HIP_TRY(hipMemsetAsync(dflags, 0, sizeof(int) * 16, st));
+  unsigned* d_amax = reinterpret_cast<unsigned*>(dflags + 4);
+  int* d_nonunit = dflags + 8;
+  if (I > 0) {
+    hipLaunchKernelGGL(validate_rows, dim3((unsigned)((I + 255) / 256)), dim3(256), 0, st, d->row_ptr, d->item_idx,
+                       d->c, d->a, I, J, m, nnz, dflags, d_amax, d_nonunit);
+    DL_HIP_TRY(hipGetLastError());
+  }
+  int hflags[16];
+  DL_HIP_TRY(hipMemcpyAsync(hflags, dflags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+  DL_HIP_TRY(hipStreamSynchronize(st));
+  DL_CHECK_ARG(!(hflags[0] & F_RANGE), "item_idx out of range [0, n_items)");
+  DL_CHECK_ARG(!(hflags[0] & F_ORDER), "item_idx must be strictly increasing within each row");
+  DL_CHECK_ARG(!(hflags[0] & F_CNAN), "c has a non-finite entry");
+  DL_CHECK_ARG(!(hflags[0] & F_ANAN), "a has a non-finite entry");
+  float amax[DL_MAX_FAMILIES] = {1.f, 1.f, 1.f, 1.f};
+  int fam_of_slot[DL_MAX_FAMILIES] = {0, 0, 0, 0};
+  P->n_stored = 0;
+  for (int k = 0; k < m; ++k) {
+    if (d->a && hflags[8 + k]) {
+      P->a_slot[k] = P->n_stored;
+      fam_of_slot[P->n_stored++] = k;
+      float mx;
+      memcpy(&mx, &hflags[4 + k], 4);
+      amax[k] = mx;
+    } else {
+      P->a_slot[k] = -1;
+      amax[k] = 1.f;
+    }
+  }
+  P->has_a = P->n_stored > 0;
+
+  // ---- library-owned layout ----
+  const bool bf16 = P->storage == DL_BF16;
+  const size_t vb = bf16 ? 2 : 4;
+  DL_TRY(dmalloc(P, &P->rp, (size_t)I + 1));
+  DL_TRY(dmalloc(P, &P->idx, (size_t)nnz));
+  {
+    unsigned char* cv = nullptr;
+    DL_TRY(dmalloc(P, &cv, (size_t)nnz * vb));
+    P->cval = cv;
+  }
+  if (P->n_stored > 0) {
+    unsigned char* av = nullptr;
+    DL_TRY(dmalloc(P, &av, (size_t)nnz * vb * (size_t)P->n_stored));
+    P->aval = av;
+  }
+  DL_TRY(dmalloc(P, &P->orig_rp, (size_t)std::max<int64_t>(I, 1)));
+  DL_TRY(dmalloc(P, &P->wg_task, (size_t)n_wg + 1));
+  DL_HIP_TRY(hipMemcpyAsync(P->rp, new_rp.data(), sizeof(int64_t) * (size_t)(I + 1), hipMemcpyHostToDevice, st));
+  if (I > 0)
+    DL_HIP_TRY(hipMemcpyAsync(P->orig_rp, orig_rp.data(), sizeof(int64_t) * (size_t)I, hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipMemcpyAsync(P->wg_task, wg_task.data(), sizeof(int64_t) * (size_t)(n_wg + 1), hipMemcpyHostToDevice,
+                            st));
+  int* d_slot = dflags + 12;  // fam_of_slot (n_stored <= 4)
+  DL_HIP_TRY(hipMemcpyAsync(d_slot, fam_of_slot, sizeof(int) * 4, hipMemcpyHostToDevice, st));
+  if (I > 0) {
+    const int64_t threads = I * 64;
+    hipLaunchKernelGGL(gather_rows, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, P->orig_rp, P->rp, I,
+                       d->item_idx, d->c, d->a, nnz, P->n_stored, d_slot, bf16 ? 1 : 0, P->idx, P->cval, P->aval);
+    DL_HIP_TRY(hipGetLastError());
+  }
+
+  // ---- item statistics: counts and the m x m blocks of A A^T per item ----
+  const int64_t mJ = (int64_t)m * J;
+  std::vector<double> esc((size_t)m * m, 0.0);
+  for (int k = 0; k < m; ++k)
+    for (int l = k; l < m; ++l) {
+      double bound = std::max<double>(1.0, (double)I) * (double)amax[k] * (double)amax[l];
+      int E = 61 - (int)ceil(log2(std::max(bound, 1e-300)));
+      esc[(size_t)k * m + l] = ldexp(1.0, E);
+    }
+  unsigned long long *d_cnt = nullptr, *d_M = nullptr;
+  double* d_esc = nullptr;
+  int* d_aslot = nullptr;
+  DL_HIP_TRY(hipMalloc((void**)&d_cnt, sizeof(unsigned long long) * (size_t)J));
+  FreeGuard g1{d_cnt};
+  DL_HIP_TRY(hipMalloc((void**)&d_M, sizeof(unsigned long long) * (size_t)J * m * m));
+  FreeGuard g2{d_M};
+  DL_HIP_TRY(hipMalloc((void**)&d_esc, sizeof(double) * (size_t)m * m + sizeof(int) * DL_MAX_FAMILIES));
+  FreeGuard g3{d_esc};
+  d_aslot = reinterpret_cast<int*>(d_esc + (size_t)m * m);
+  DL_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * (size_t)J, st));
+  DL_HIP_TRY(hipMemsetAsync(d_M, 0, sizeof(unsigned long long) * (size_t)J * m * m, st));
+  DL_HIP_TRY(hipMemcpyAsync(d_esc, esc.data(), sizeof(double) * (size_t)m * m, hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipMemcpyAsync(d_aslot, P->a_slot, sizeof(int) * DL_MAX_FAMILIES, hipMemcpyHostToDevice, st));
+  if (nnz > 0) {
+    int blocks = (int)std::min<int64_t>((nnz + 255) / 256, (int64_t)n_cu * 64);
+    if (bf16)
+      hipLaunchKernelGGL(item_stats<uint16_t>, dim3(blocks), dim3(256), 0, st, P->idx, P->aval, nnz, J, m, d_aslot,
+                         d_esc, d_cnt, d_M);
+    else
+      hipLaunchKernelGGL(item_stats<float>, dim3(blocks), dim3(256), 0, st, P->idx, P->aval, nnz, J, m, d_aslot,
+                         d_esc, d_cnt, d_M);
+    DL_HIP_TRY(hipGetLastError());
+  }
+  std::vector<unsigned long long> cnt((size_t)J), Mq((size_t)J * m * m);
+  DL_HIP_TRY(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(unsigned long long) * (size_t)J, hipMemcpyDeviceToHost, st));
+  DL_HIP_TRY(hipMemcpyAsync(Mq.data(), d_M, sizeof(unsigned long long) * (size_t)J * m * m, hipMemcpyDeviceToHost,
+                            st));
+  DL_HIP_TRY(hipStreamSynchronize(st));
+
+  // M_j[k][l] in FP64, D = diag(1/||A_kj||_2) (1 on zero rows), lhat >= ||DA||^2
+  auto Mkl = [&](int32_t j, int k, int l) -> double {
+    if (k > l) std::swap(k, l);
+    if (P->a_slot[k] < 0 && P->a_slot[l] < 0) return (double)cnt[(size_t)j];
+    long long q = (long long)Mq[((size_t)j * m + k) * m + l];
+    return (double)q / esc[(size_t)k * m + l];
+  };
+  P->D_host.assign((size_t)mJ, 1.0);
+  if (P->jacobi) {
+    for (int k = 0; k < m; ++k)
+      for (int32_t j = 0; j < J; ++j) {
+        double n2 = Mkl(j, k, k);
+        P->D_host[(size_t)k * J + j] = n2 > 0.0 ? 1.0 / sqrt(n2) : 1.0;
+      }
+  }
+  double L = 0.0;
+  for (int32_t j = 0; j < J; ++j)
+    for (int k = 0; k < m; ++k) {
+      double row = 0.0;
+      for (int l = 0; l < m; ++l)
+        row += fabs(P->D_host[(size_t)k * J + j] * Mkl(j, k, l) * P->D_host[(size_t)l * J + j]);
+      L = std::max(L, row);
+    }
+  P->lhat = L > 0.0 ? L : 1.0;
+
+  // fixed-point grid of each family's accumulation: |a x| <= amax * radius -> 2^30
+  for (int k = 0; k < m; ++k) {
+    double bound = (double)amax[k] * d->radius;
+    int t = 30 - (int)ceil(log2(std::max(bound, 1e-30)));
+    P->qscale[k] = (float)ldexp(1.0, t);
+  }
+
+  // ---- item space and scratch ----
+  P->b_host.assign(d->b, d->b + mJ);
+  DL_TRY(dmalloc(P, &P->b, (size_t)mJ));
+  DL_TRY(dmalloc(P, &P->D, (size_t)mJ));
+  DL_HIP_TRY(hipMemcpyAsync(P->b, P->b_host.data(), sizeof(double) * (size_t)mJ, hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipMemcpyAsync(P->D, P->D_host.data(), sizeof(double) * (size_t)mJ, hipMemcpyHostToDevice, st));
+  DL_TRY(dmalloc(P, &P->part, (size_t)std::max(1, P->n_wg) * (size_t)mJ));
+  DL_TRY(dmalloc(P, &P->obj_part, (size_t)std::max(1, P->n_wg)));
+  DL_TRY(dmalloc(P, &P->pobj_part, (size_t)std::max(1, P->n_wg)));
+  DL_TRY(dmalloc(P, &P->mu, (size_t)mJ));
+  DL_TRY(dmalloc(P, &P->rfac, (size_t)J));
+  DL_TRY(dmalloc(P, &P->lam_tmp, (size_t)mJ));
+  DL_TRY(dmalloc(P, &P->cert_out, 16));
+  DL_HIP_TRY(hipHostMalloc((void**)&P->cert_host, sizeof(double) * 16, hipHostMallocDefault));
+  DL_TRY(dl_grad_prepare(P));
+  DL_HIP_TRY(hipStreamSynchronize(st));
+  return DL_OK;
+}
+
+}  // namespace
+
+extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** out) {
+  if (!out) {
+    dl_set_error("out is NULL");
+    return DL_EINVAL;
+  }
+  *out = nullptr;
+  DL_CHECK_ARG(d != nullptr, "desc is NULL");
+  DL_CHECK_ARG(d->n_users >= 0 && d->n_users < ((int64_t)1 << 40), "n_users out of range");
+  DL_CHECK_ARG(d->n_items >= 1, "n_items must be >= 1");
+  DL_CHECK_ARG(d->n_families >= 1 && d->n_families <= DL_MAX_FAMILIES, "n_families must be in 1..4");
+  DL_CHECK_ARG(d->row_ptr && d->b, "row_ptr and b are required");
+  DL_CHECK_ARG(d->proj >= DL_PROJ_SIMPLEX_LE && d->proj <= DL_PROJ_BOX, "unknown projection kind");
+  DL_CHECK_ARG(d->storage == DL_F32 || d->storage == DL_BF16, "unknown storage");
+  DL_CHECK_ARG(d->radius > 0.0 && isfinite(d->radius), "radius must be positive and finite");
+  const int64_t mJ = (int64_t)d->n_items * d->n_families;
+  for (int64_t r = 0; r < mJ; ++r) DL_CHECK_ARG(isfinite(d->b[r]), "b has a non-finite entry");
+  if (mJ > DL_MAX_MJ) {
+    dl_set_error("n_families * n_items exceeds the on-chip accumulation capacity (13000)");
+    return DL_EUNSUPPORTED;
+  }
+  dl_problem* P = new (std::nothrow) dl_problem();
+  if (!P) {
+    dl_set_error("host allocation failed");
+    return DL_ENOMEM;
+  }
+  dl_status s = create_impl(d, P);
+  if (s != DL_OK) {
+    free_problem(P);
+    return s;
+  }
+  *out = P;
+  return DL_OK;
+}
+
+extern "C" void dl_problem_destroy(dl_problem* P) { free_problem(P); }
+
+extern "C" dl_status dl_problem_get_info(const dl_problem* P, dl_problem_info* o) {
+  DL_CHECK_ARG(P && o, "NULL argument");
+  memset(o, 0, sizeof(*o));
+  o->n_users = P->I;
+  o->nnz = P->nnz;
+  o->n_items = P->J;
+  o->n_families = P->m;
+  o->n_stored_families = P->n_stored;
+  o->n_workgroups = P->n_wg;
+  o->n_tasks = P->n_tasks;
+  o->lhat = P->lhat;
+  const double vb = P->storage == DL_BF16 ? 2.0 : 4.0;
+  // per nnz: item index + c + stored a's; per user: row pointer; per item: lam in, partial sums out
+  o->bytes_per_pass = (double)P->nnz * (4.0 + vb * (1 + P->n_stored)) + 8.0 * (double)(P->I + 1) +
+                      (double)P->m * P->J * 4.0;
+  o->device_bytes = P->device_bytes;
+  o->max_degree = P->max_degree;
+  o->n_buckets = (int32_t)P->buckets.size();
+  for (size_t i = 0; i < P->buckets.size() && i < 8; ++i) {
+    o->bucket_glog[i] = P->buckets[i].glog;
+    o->bucket_users[i] = P->buckets[i].user_end - P->buckets[i].user_begin;
+  }
+  for (int k = 0; k < DL_MAX_FAMILIES; ++k) o->qscale[k] = P->qscale[k];
+  return DL_OK;
+}

@@ -1,0 +1,502 @@
+// Item-space kernels and the Maximizer of the dual ascent (Sections 4.4 and 6,
+// Appendix C): fixed-order reduction of the per-workgroup partial sums, the
+// accelerated projected step on lam >= 0 in Jacobi-scaled units, the
+// certificate (feasible repair, primal and dual values, gap, slack), and the
+// host loop over the gamma schedule.
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <utility>
+
+#include "dl_common.h"
+
+namespace {
+
+struct upd_args {
+  const unsigned long long* part;
+  int n_wg;
+  int mJ, J;
+  double inv_q[DL_MAX_FAMILIES];
+  const double* D;
+  const double* b;
+  double* lam;      // scaled lam'
+  double* y;        // scaled momentum point y'
+  float* mu_y;      // FP32 D y' (problem units), gathered by the next pass
+  float* mu_lam;    // FP32 D lam'
+  double eta, beta;
+  int* flag;
+  double* ax_out;   // nullable: A x (problem units)
+  double* grad_out; // nullable: A x - b
+};
+
+__device__ __forceinline__ double sum_partials(const unsigned long long* part, int n_wg, int mJ, int r) {
+  long long acc = 0;
+  for (int w = 0; w < n_wg; ++w) acc += (long long)part[(size_t)w * mJ + r];
+  return (double)acc;
+}
+
+// Fused accelerated step: reduce the gradient at y', take
+// lam'_+ = max(0, y' + eta D (A x - b)), y'_+ = lam'_+ + beta (lam'_+ - lam'),
+// and publish the next gather point D y'_+ (FP32).
+__global__ void update_kernel(upd_args U) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= U.mJ) return;
+  const int k = r / U.J;
+  const double ax = sum_partials(U.part, U.n_wg, U.mJ, r) * U.inv_q[k];
+  const double Dr = U.D[r];
+  const double gs = Dr * (ax - U.b[r]);
+  const double lo = U.lam[r];
+  const double ln = fmax(0.0, U.y[r] + U.eta * gs);
+  const double yn = ln + U.beta * (ln - lo);
+  U.lam[r] = ln;
+  U.y[r] = yn;
+  U.mu_y[r] = (float)(Dr * yn);
+  U.mu_lam[r] = (float)(Dr * ln);
+  if (!isfinite(ln) || !isfinite(yn)) atomicOr(U.flag, 1);
+}
+
+// A x (and A x - b) from the partials, no step.
+__global__ void reduce_kernel(upd_args U) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= U.mJ) return;
+  const int k = r / U.J;
+  const double ax = sum_partials(U.part, U.n_wg, U.mJ, r) * U.inv_q[k];
+  if (U.ax_out) U.ax_out[r] = ax;
+  if (U.grad_out) U.grad_out[r] = ax - U.b[r];
+}
+
+// lam' = max(0, lam0 / D), y' = lam', gather points; or (lam0 == NULL) zeros.
+__global__ void init_state(const double* lam0, const double* D, int mJ, double* lam, double* y, float* mu_y,
+                           float* mu_lam) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mJ) return;
+  double l = lam0 ? fmax(0.0, lam0[r] / D[r]) : 0.0;
+  lam[r] = l;
+  y[r] = l;
+  float m = (float)(D[r] * l);
+  mu_y[r] = m;
+  mu_lam[r] = m;
+}
+
+// Momentum restart at a stage switch: y' = lam'.
+__global__ void reset_momentum(const double* D, int mJ, const double* lam, double* y, float* mu_y) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mJ) return;
+  y[r] = lam[r];
+  mu_y[r] = (float)(D[r] * lam[r]);
+}
+
+__global__ void scaled_to_units(const double* D, int mJ, const double* lam, double* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mJ) return;
+  out[r] = D[r] * lam[r];
+}
+
+__global__ void to_f32(const double* in, int n, float* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = (float)in[r];
+}
+
+// Deterministic block reduction helpers (fixed tree over 1024 threads).
+__device__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__device__ double block_max(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Certificate, item part (one workgroup): repair factor r_j =
+// min_k min(1, b_kj / (A_k x)_j), max slack, lam.b and -lam.(Ax - b) at the
+// FP32 point mu the pass used, and the Lagrangian sum over workgroups.
+//   out[0] = sum_w obj_part[w] - mu.b   (dual value g(mu))
+//   out[1] = max_r (A x - b)_r^+
+//   out[2] = -mu.(A x - b)
+__global__ void cert_items(const double* ax, const double* b, const float* mu, int m, int J, const double* obj_part,
+                           int n_wg, float* rfac, double* out) {
+  __shared__ double sh[1024];
+  double lb = 0.0, slack = 0.0, lg = 0.0;
+  for (int j = threadIdx.x; j < J; j += blockDim.x) {
+    double rj = 1.0;
+    for (int k = 0; k < m; ++k) {
+      const int r = k * J + j;
+      const double viol = ax[r] - b[r];
+      slack = fmax(slack, viol);
+      lb += (double)mu[r] * b[r];
+      lg -= (double)mu[r] * viol;
+      if (ax[r] > b[r]) rj = fmin(rj, b[r] > 0.0 ? b[r] / ax[r] : 0.0);
+    }
+    rfac[j] = (float)rj;
+  }
+  double os = 0.0;
+  for (int w = threadIdx.x; w < n_wg; w += blockDim.x) os += obj_part[w];
+  lb = block_sum(lb, sh);
+  lg = block_sum(lg, sh);
+  os = block_sum(os, sh);
+  slack = block_max(slack, sh);
+  if (threadIdx.x == 0) {
+    out[0] = os - lb;
+    out[1] = slack;
+    out[2] = lg;
+  }
+}
+
+// out[3] = sum_w pobj_part[w]   (primal value of the repaired point)
+__global__ void cert_final(const double* pobj_part, int n_wg, double* out) {
+  __shared__ double sh[1024];
+  double s = 0.0;
+  for (int w = threadIdx.x; w < n_wg; w += blockDim.x) s += pobj_part[w];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[3] = s;
+}
+
+inline unsigned blocks_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+struct dl_solver {
+  dl_problem* P = nullptr;
+  double* lam = nullptr;   // m*J scaled
+  double* y = nullptr;
+  double* ax = nullptr;    // certificate scratch
+  float* mu_y = nullptr;
+  float* mu_lam = nullptr;
+  int* flag = nullptr;
+  double gamma = 1.0, eta = 1.0, tk = 1.0;
+  int64_t iters = 0;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_grad, ev_upd;
+  size_t n_ev_grad = 0, n_ev_upd = 0;
+};
+
+namespace {
+
+upd_args make_upd(const dl_problem* P) {
+  upd_args U;
+  memset(&U, 0, sizeof(U));
+  U.part = P->part;
+  U.n_wg = P->n_wg;
+  U.mJ = P->m * P->J;
+  U.J = P->J;
+  for (int k = 0; k < DL_MAX_FAMILIES; ++k) U.inv_q[k] = P->qscale[k] > 0.f ? 1.0 / (double)P->qscale[k] : 0.0;
+  U.D = P->D;
+  U.b = P->b;
+  return U;
+}
+
+dl_status next_event_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, size_t& n,
+                          std::pair<hipEvent_t, hipEvent_t>** out) {
+  if (n == v.size()) {
+    hipEvent_t a, b;
+    DL_HIP_TRY(hipEventCreate(&a));
+    DL_HIP_TRY(hipEventCreate(&b));
+    v.emplace_back(a, b);
+  }
+  *out = &v[n++];
+  return DL_OK;
+}
+
+// Certificate at the solver's current lam (Table 4 metrics, certified gap).
+dl_status certificate(dl_solver* S, dl_solve_stats* st) {
+  dl_problem* P = S->P;
+  const int mJ = P->m * P->J;
+  DL_TRY(dl_launch_grad(P, M_HIST | M_OBJ, S->mu_lam, S->gamma, nullptr, nullptr, nullptr, P->obj_part));
+  upd_args U = make_upd(P);
+  U.ax_out = S->ax;
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
+  DL_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(cert_items, dim3(1), dim3(1024), 0, P->stream, S->ax, P->b, S->mu_lam, P->m, P->J,
+                     P->obj_part, P->n_wg, P->rfac, P->cert_out);
+  DL_HIP_TRY(hipGetLastError());
+  DL_TRY(dl_launch_grad(P, M_REPAIR, S->mu_lam, S->gamma, P->rfac, nullptr, nullptr, P->pobj_part));
+  hipLaunchKernelGGL(cert_final, dim3(1), dim3(1024), 0, P->stream, P->pobj_part, P->n_wg, P->cert_out);
+  DL_HIP_TRY(hipGetLastError());
+  DL_HIP_TRY(hipMemcpyAsync(P->cert_host, P->cert_out, sizeof(double) * 4, hipMemcpyDeviceToHost, P->stream));
+  int hflag = 0;
+  DL_HIP_TRY(hipMemcpyAsync(&hflag, S->flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  DL_HIP_TRY(hipStreamSynchronize(P->stream));
+  const double g = P->cert_host[0], pobj = P->cert_host[3];
+  st->gamma = S->gamma;
+  st->dual_obj = g;
+  st->primal_obj = pobj;
+  st->rel_gap = (pobj - g) / fmax(1.0, fabs(g));
+  st->max_slack = P->cert_host[1];
+  st->lagr_gap = P->cert_host[2];
+  st->iters = S->iters;
+  if (hflag) {
+    dl_set_error("non-finite dual iterate");
+    return DL_DIVERGED;
+  }
+  if (!isfinite(g) || !isfinite(pobj)) {
+    dl_set_error("non-finite dual objective or certificate");
+    return DL_NUMERIC;
+  }
+  return DL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ObjectiveFunction and ProjectionMap
+// ---------------------------------------------------------------------------
+extern "C" dl_status dl_dual_grad(dl_problem* P, const double* lambda, double gamma, double* grad, double* dual_obj,
+                                  float* x) {
+  DL_CHECK_ARG(P && lambda, "NULL argument");
+  DL_CHECK_ARG(gamma > 0.0 && isfinite(gamma), "gamma must be positive and finite");
+  const int mJ = P->m * P->J;
+  hipLaunchKernelGGL(to_f32, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, lambda, mJ, P->mu);
+  DL_HIP_TRY(hipGetLastError());
+  const bool want_obj = dual_obj != nullptr;
+  DL_TRY(dl_launch_grad(P, want_obj ? (M_HIST | M_OBJ) : M_HIST, P->mu, gamma, nullptr, nullptr, x, P->obj_part));
+  upd_args U = make_upd(P);
+  U.ax_out = P->lam_tmp;
+  U.grad_out = grad;
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
+  DL_HIP_TRY(hipGetLastError());
+  if (want_obj) {
+    hipLaunchKernelGGL(cert_items, dim3(1), dim3(1024), 0, P->stream, P->lam_tmp, P->b, P->mu, P->m, P->J,
+                       P->obj_part, P->n_wg, P->rfac, P->cert_out);
+    DL_HIP_TRY(hipGetLastError());
+    DL_HIP_TRY(hipMemcpyAsync(P->cert_host, P->cert_out, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    DL_HIP_TRY(hipStreamSynchronize(P->stream));
+    *dual_obj = P->cert_host[0];
+  }
+  return DL_OK;
+}
+
+extern "C" dl_status dl_project(dl_problem* P, const float* v, float* x) {
+  DL_CHECK_ARG(P && ((v && x) || P->nnz == 0), "NULL argument");
+  return dl_launch_grad(P, M_VIN, nullptr, 1.0, nullptr, v, x, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Maximizer
+// ---------------------------------------------------------------------------
+extern "C" dl_status dl_solver_create(dl_problem* P, const double* lambda0, dl_solver** out) {
+  DL_CHECK_ARG(P && out, "NULL argument");
+  *out = nullptr;
+  dl_solver* S = new (std::nothrow) dl_solver();
+  if (!S) {
+    dl_set_error("host allocation failed");
+    return DL_ENOMEM;
+  }
+  S->P = P;
+  const int mJ = P->m * P->J;
+  auto fail = [&](dl_status s) {
+    dl_solver_destroy(S);
+    return s;
+  };
+  if (hipMalloc((void**)&S->lam, sizeof(double) * mJ) != hipSuccess ||
+      hipMalloc((void**)&S->y, sizeof(double) * mJ) != hipSuccess ||
+      hipMalloc((void**)&S->ax, sizeof(double) * mJ) != hipSuccess ||
+      hipMalloc((void**)&S->mu_y, sizeof(float) * mJ) != hipSuccess ||
+      hipMalloc((void**)&S->mu_lam, sizeof(float) * mJ) != hipSuccess ||
+      hipMalloc((void**)&S->flag, sizeof(int)) != hipSuccess) {
+    dl_set_error("device allocation failed");
+    return fail(DL_ENOMEM);
+  }
+  if (hipMemsetAsync(S->flag, 0, sizeof(int), P->stream) != hipSuccess) return fail(DL_EHIP);
+  hipLaunchKernelGGL(init_state, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, lambda0, P->D, mJ, S->lam, S->y,
+                     S->mu_y, S->mu_lam);
+  if (hipGetLastError() != hipSuccess) {
+    dl_set_error("init_state launch failed");
+    return fail(DL_EHIP);
+  }
+  *out = S;
+  return DL_OK;
+}
+
+extern "C" void dl_solver_destroy(dl_solver* S) {
+  if (!S) return;
+  void* ptrs[] = {S->lam, S->y, S->ax, S->mu_y, S->mu_lam, S->flag};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (auto& e : S->ev_grad) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : S->ev_upd) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  delete S;
+}
+
+extern "C" dl_status dl_solver_set_stage(dl_solver* S, double gamma, double step_scale, int32_t reset) {
+  DL_CHECK_ARG(S, "NULL solver");
+  DL_CHECK_ARG(gamma > 0.0 && isfinite(gamma), "gamma must be positive and finite");
+  DL_CHECK_ARG(step_scale > 0.0 && isfinite(step_scale), "step_scale must be positive");
+  dl_problem* P = S->P;
+  S->gamma = gamma;
+  S->eta = step_scale * gamma / P->lhat;  // step proportional to gamma (L <= ||A'||^2/gamma)
+  if (reset) {
+    S->tk = 1.0;
+    const int mJ = P->m * P->J;
+    hipLaunchKernelGGL(reset_momentum, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, P->D, mJ, S->lam, S->y,
+                       S->mu_y);
+    DL_HIP_TRY(hipGetLastError());
+  }
+  return DL_OK;
+}
+
+extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
+  DL_CHECK_ARG(S && n >= 0, "bad argument");
+  dl_problem* P = S->P;
+  const int mJ = P->m * P->J;
+  upd_args U = make_upd(P);
+  U.lam = S->lam;
+  U.y = S->y;
+  U.mu_y = S->mu_y;
+  U.mu_lam = S->mu_lam;
+  U.eta = S->eta;
+  U.flag = S->flag;
+  for (int64_t it = 0; it < n; ++it) {
+    std::pair<hipEvent_t, hipEvent_t>* eg = nullptr;
+    if (S->timing) {
+      DL_TRY(next_event_pair(S->ev_grad, S->n_ev_grad, &eg));
+      DL_HIP_TRY(hipEventRecord(eg->first, P->stream));
+    }
+    DL_TRY(dl_launch_grad(P, M_HIST, S->mu_y, S->gamma, nullptr, nullptr, nullptr, nullptr));
+    std::pair<hipEvent_t, hipEvent_t>* eu = nullptr;
+    if (S->timing) {
+      DL_HIP_TRY(hipEventRecord(eg->second, P->stream));
+      DL_TRY(next_event_pair(S->ev_upd, S->n_ev_upd, &eu));
+      DL_HIP_TRY(hipEventRecord(eu->first, P->stream));
+    }
+    // FISTA momentum: t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, beta = (t_k - 1) / t_{k+1}
+    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S->tk * S->tk));
+    U.beta = (S->tk - 1.0) / tn;
+    S->tk = tn;
+    hipLaunchKernelGGL(update_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
+    DL_HIP_TRY(hipGetLastError());
+    if (S->timing) DL_HIP_TRY(hipEventRecord(eu->second, P->stream));
+    ++S->iters;
+  }
+  return DL_OK;
+}
+
+extern "C" dl_status dl_solver_get_lambda(dl_solver* S, double* out) {
+  DL_CHECK_ARG(S && out, "NULL argument");
+  dl_problem* P = S->P;
+  const int mJ = P->m * P->J;
+  hipLaunchKernelGGL(scaled_to_units, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, P->D, mJ, S->lam, out);
+  DL_HIP_TRY(hipGetLastError());
+  return DL_OK;
+}
+
+extern "C" dl_status dl_solver_certificate(dl_solver* S, dl_solve_stats* out) {
+  DL_CHECK_ARG(S && out, "NULL argument");
+  memset(out, 0, sizeof(*out));
+  dl_status s = certificate(S, out);
+  out->status = s;
+  return s;
+}
+
+extern "C" dl_status dl_solver_enable_timing(dl_solver* S, int32_t on) {
+  DL_CHECK_ARG(S, "NULL solver");
+  S->timing = on != 0;
+  S->n_ev_grad = S->n_ev_upd = 0;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_solver_get_timing(dl_solver* S, dl_timing* out) {
+  DL_CHECK_ARG(S && out, "NULL argument");
+  DL_HIP_TRY(hipStreamSynchronize(S->P->stream));
+  memset(out, 0, sizeof(*out));
+  for (size_t i = 0; i < S->n_ev_grad; ++i) {
+    float ms = 0.f;
+    DL_HIP_TRY(hipEventElapsedTime(&ms, S->ev_grad[i].first, S->ev_grad[i].second));
+    out->grad_ms_total += ms;
+  }
+  for (size_t i = 0; i < S->n_ev_upd; ++i) {
+    float ms = 0.f;
+    DL_HIP_TRY(hipEventElapsedTime(&ms, S->ev_upd[i].first, S->ev_upd[i].second));
+    out->update_ms_total += ms;
+  }
+  out->n_grad = (int64_t)S->n_ev_grad;
+  out->n_update = (int64_t)S->n_ev_upd;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const double* lambda0, double* lambda_out,
+                              dl_solve_stats* st) {
+  DL_CHECK_ARG(P && o && st && lambda_out, "NULL argument");
+  DL_CHECK_ARG(o->n_stages >= 1 && o->gammas && o->iters, "empty schedule");
+  for (int s = 0; s < o->n_stages; ++s) {
+    DL_CHECK_ARG(o->gammas[s] > 0.0 && isfinite(o->gammas[s]), "gamma must be positive and finite");
+    DL_CHECK_ARG(o->iters[s] >= 0 || s == o->n_stages - 1, "only the last stage may run until tol");
+  }
+  DL_CHECK_ARG(o->max_iters >= 0 && o->check_every >= 0, "negative limits");
+  const double step_scale = o->step_scale > 0.0 ? o->step_scale : 1.0;
+  auto t0 = std::chrono::steady_clock::now();
+  memset(st, 0, sizeof(*st));
+  dl_solver* S = nullptr;
+  DL_TRY(dl_solver_create(P, lambda0, &S));
+  dl_status rc = DL_OK;
+  bool converged = false;
+  int64_t n_checks = 0;
+  int stage = 0;
+  for (stage = 0; stage < o->n_stages && rc == DL_OK && !converged; ++stage) {
+    rc = dl_solver_set_stage(S, o->gammas[stage], step_scale, stage == 0 ? 1 : o->reset_momentum);
+    if (rc != DL_OK) break;
+    const bool last = stage == o->n_stages - 1;
+    const int64_t n_it = o->iters[stage];
+    int64_t done = 0;
+    while ((n_it < 0 || done < n_it) && S->iters < o->max_iters) {
+      int64_t chunk = (n_it < 0) ? o->max_iters - S->iters : n_it - done;
+      if (last && o->check_every > 0) chunk = std::min<int64_t>(chunk, o->check_every - (done % o->check_every));
+      chunk = std::min<int64_t>(chunk, o->max_iters - S->iters);
+      rc = dl_solver_step(S, chunk);
+      if (rc != DL_OK) break;
+      done += chunk;
+      if (last && o->check_every > 0 && done % o->check_every == 0) {
+        rc = certificate(S, st);
+        ++n_checks;
+        if (rc != DL_OK) break;
+        if (st->rel_gap <= o->tol) {
+          converged = true;
+          break;
+        }
+      }
+      if (n_it < 0 && o->check_every == 0) break;  // nothing would ever stop it
+    }
+    if (S->iters >= o->max_iters) {
+      ++stage;
+      break;
+    }
+  }
+  if (rc == DL_OK && !converged) {
+    rc = certificate(S, st);
+    ++n_checks;
+    if (rc == DL_OK) converged = st->rel_gap <= o->tol;
+  }
+  dl_status lrc = dl_solver_get_lambda(S, lambda_out);
+  if (rc == DL_OK) rc = lrc;
+  if (rc == DL_OK) DL_HIP_TRY(hipStreamSynchronize(P->stream));
+  st->iters = S->iters;
+  st->stage = stage - 1;
+  st->n_checks = n_checks;
+  st->status = (rc == DL_OK) ? (converged ? DL_OK : DL_NOT_CONVERGED) : rc;
+  st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  dl_solver_destroy(S);
+  if (rc != DL_OK) return rc;
+  return converged ? DL_OK : DL_NOT_CONVERGED;
+}

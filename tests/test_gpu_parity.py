@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances follow from the arithmetic of the FP32 path.  The GPU forms
+v = (c + sum_k a_k mu_k) * (-1/gamma) in FP32 (relative error <= 3 u, u = 2^-24)
+and the threshold theta from FP32 sums over one row, so per element
+|x_gpu - x_fp64| <= 32 u max_i|v| for the user's row (a generous multiple of the
+few roundings involved).  Each a_k x is then rounded to a fixed-point grid of
+step 1/qscale_k (<= 2^-30 for a <= 1, z = 1) and summed exactly in 64-bit
+integers, so (A x)_j carries at most sum_i |a_ij| (32 u max|v| + 1/qscale)
+error.  Both sides evaluate at the same point mu = fl32(lambda).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def dl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_07777_amd as dl
+    dl.load()
+    return dl
+
+
+def _cases(wl):
+    return {
+        "tiny_plain_binding": (wl.tiny_plain(seed=0, binding=True), 1e-2),
+        "all_buckets_long_rows": (wl.random_small(51, 3000, 3500, 3000, b_scale=0.2), 5e-2),
+        "two_family_box": (wl.random_small(52, 5000, 300, 200, n_families=2, a_ones=False, proj="box"), 2e-2),
+        "simplex_eq": (wl.random_small(53, 4000, 200, 150, proj="simplex_eq"), 1e-2),
+        "explicit_a": (wl.random_small(54, 4000, 500, 300, a_ones=False), 1e-2),
+        "production_small": (wl.production(n_users=100_000, n_items=10_000), 1e-2),
+    }
+
+
+CASE_NAMES = ["tiny_plain_binding", "all_buckets_long_rows", "two_family_box", "simplex_eq", "explicit_a",
+              "production_small"]
+
+
+@pytest.fixture(scope="module")
+def cases(wl):
+    return _cases(wl)
+
+
+def _lam_point(orc, inst, gamma, seed):
+    """A realistic dual point: 40 oracle iterations from 0, plus noise."""
+    lam, _, _, _ = orc.solve(inst, [gamma], [40], jacobi=True, check_every=0)
+    rng = np.random.default_rng(seed)
+    return np.maximum(0.0, lam * (1 + 0.1 * rng.normal(size=lam.size)) + 0.01 * rng.uniform(size=lam.size))
+
+
+def _row_vmax(inst, lam32, gamma):
+    """max_e |v_e| per row, in FP64, for the error bounds."""
+    a = inst.a_dense().astype(np.float64)
+    s = np.zeros(inst.nnz)
+    for k in range(inst.n_families):
+        s += a[k] * lam32[k * inst.n_items + inst.item_idx]
+    v = np.abs(inst.c.astype(np.float64) + s) / gamma
+    assert np.all(np.diff(inst.row_ptr) > 0), "parity instances have no empty rows"
+    return np.maximum.reduceat(v, inst.row_ptr[:-1]), v
+
+
+@pytest.mark.parametrize("name", CASE_NAMES)
+def test_dual_grad_matches_oracle(dl, orc, cases, name):
+    import torch
+    inst, gamma = cases[name]
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    lam = _lam_point(orc, inst, gamma, 1)
+    lam32 = lam.astype(np.float32).astype(np.float64)
+    g, grad, x = prob.dual_grad(torch.from_numpy(lam), gamma, want_obj=True, want_x=True)
+    grad, x = grad.cpu().numpy(), x.cpu().numpy()
+    go, grad_o, x_o, ax_o = orc.dual_grad(inst, lam32, gamma)
+    deg = inst.degrees()
+    vmax_row, _ = _row_vmax(inst, lam32, gamma)
+    vmax_el = np.repeat(vmax_row, deg)
+    xerr = np.abs(x - x_o)
+    xtol = 32 * U32 * np.maximum(vmax_el, 1.0)
+    assert np.all(xerr <= xtol), f"x err {xerr.max():.3e} (worst ratio {(xerr / xtol).max():.2f})"
+    a = inst.a_dense().astype(np.float64)
+    qs = np.array(prob.info()["qscale"], dtype=np.float64)
+    for k in range(inst.n_families):
+        J = inst.n_items
+        bound = np.bincount(inst.item_idx, weights=np.abs(a[k]) * (xtol + 1.0 / qs[k]), minlength=J)
+        err = np.abs(grad[k * J:(k + 1) * J] - grad_o[k * J:(k + 1) * J])
+        assert np.all(err <= bound + 1e-12), f"family {k}: grad err {err.max():.3e}"
+    rel = np.linalg.norm(grad - grad_o) / max(np.linalg.norm(ax_o), 1e-30)
+    assert rel <= 2e-6, rel
+    assert abs(g - go) <= 2e-6 * max(1.0, abs(go)), (g, go)
+    print(f"{name}: nnz {inst.nnz} x err {xerr.max():.2e} grad rel {rel:.2e} dual rel {abs(g - go) / abs(go):.2e}")
+
+
+@pytest.mark.parametrize("name", ["tiny_plain_binding", "all_buckets_long_rows", "simplex_eq", "two_family_box"])
+def test_project_matches_oracle(dl, orc, cases, name):
+    import torch
+    inst, _ = cases[name]
+    prob = dl.Problem.from_instance(inst)
+    rng = np.random.default_rng(7)
+    v = (rng.normal(size=inst.nnz) * 3).astype(np.float32)
+    x = prob.project(torch.from_numpy(v)).cpu().numpy()
+    xo = orc.project_rows(inst, v.astype(np.float64))
+    vmax = np.maximum.reduceat(np.abs(v.astype(np.float64)), inst.row_ptr[:-1])
+    tol = 32 * U32 * np.maximum(np.repeat(vmax, inst.degrees()), 1.0)
+    assert np.all(np.abs(x - xo) <= tol), np.abs(x - xo).max()
+
+
+def test_trajectory_tiny_plain_binding(dl, orc, cases):
+    """200 iterations at gamma = 1e-2 with step 1/L from the row-norm bound, no Jacobi."""
+    import torch
+    inst, gamma = cases["tiny_plain_binding"]
+    prob = dl.Problem.from_instance(inst, jacobi=False)
+    s = prob.solver()
+    s.set_stage(gamma, 1.0, True)
+    lam_gpu = {}
+    done = 0
+    for k in (50, 100, 200):
+        s.step(k - done)
+        done = k
+        lam_gpu[k] = s.lam().cpu().numpy()
+    _, _, snaps, _ = orc.solve(inst, [gamma], [200], jacobi=False, check_every=0, snap_iters=[50, 100, 200])
+    for i, k in enumerate((50, 100, 200)):
+        rel = np.linalg.norm(lam_gpu[k] - snaps[i]) / np.linalg.norm(snaps[i])
+        print(f"iteration {k}: rel lam err {rel:.3e}")
+        assert rel <= 1e-5, (k, rel)
+
+
+def test_literal_capacities_stay_slack(dl, orc, wl):
+    import torch
+    inst = wl.tiny_plain(seed=0, binding=False)
+    prob = dl.Problem.from_instance(inst, jacobi=False)
+    lam, st = prob.solve([1e-2], [200], check_every=0)
+    assert torch.all(lam == 0).item()
+    _, _, x = prob.dual_grad(lam, 1e-2, want_obj=False, want_x=True)
+    xo = orc.project_rows(inst, -inst.c.astype(np.float64) / 1e-2)
+    assert np.abs(x.cpu().numpy() - xo).max() <= 32 * U32 * 100
+
+
+def test_continuation_solve_matches_oracle(dl, orc, wl):
+    inst = wl.tiny_plain(seed=1, binding=True, n_users=20_000, n_items=200)
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    sched = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[300, 300, -1])
+    lam, st = prob.solve(**sched, tol=1e-4, max_iters=20000, check_every=10)
+    lo, so, _, _ = orc.solve(inst, sched["gammas"], sched["iters"], tol=1e-4, max_iters=20000, check_every=10,
+                             jacobi=True)
+    assert st["status"] == 0 and so["status"] == 0
+    assert st["rel_gap"] <= 1e-4
+    # both certified to 1e-4: their dual values agree to the certified tolerance
+    assert abs(st["dual_obj"] - so["dual_obj"]) <= 2e-4 * abs(so["dual_obj"])
+    print(f"gpu iters {st['iters']} gap {st['rel_gap']:.2e}; oracle iters {so['iters']} gap {so['rel_gap']:.2e}")
+
+
+def test_bitwise_deterministic(dl, cases):
+    inst, gamma = cases["production_small"]
+    out = []
+    for _ in range(2):
+        prob = dl.Problem.from_instance(inst, jacobi=True)
+        lam, _ = prob.solve([1e-1, 1e-2], [30, 30], check_every=0)
+        out.append(lam.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_split_equals_uninterrupted(dl, cases):
+    inst, gamma = cases["tiny_plain_binding"]
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    a = prob.solver()
+    a.set_stage(gamma)
+    a.step(60)
+    b = prob.solver()
+    b.set_stage(gamma)
+    b.step(25)
+    b.step(35)
+    assert np.array_equal(a.lam().cpu().numpy(), b.lam().cpu().numpy())
