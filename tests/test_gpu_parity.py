@@ -89,8 +89,10 @@ def test_dual_grad_matches_oracle(dl, orc, cases, name):
         bound = np.bincount(inst.item_idx, weights=np.abs(a[k]) * (xtol + 1.0 / qs[k]), minlength=J)
         err = np.abs(grad[k * J:(k + 1) * J] - grad_o[k * J:(k + 1) * J])
         assert np.all(err <= bound + 1e-12), f"family {k}: grad err {err.max():.3e}"
+    # norm-wise sanity on top of the elementwise bounds above (rows of up to 3000
+    # FP32 terms reach a few 1e-6)
     rel = np.linalg.norm(grad - grad_o) / max(np.linalg.norm(ax_o), 1e-30)
-    assert rel <= 2e-6, rel
+    assert rel <= 1e-5, rel
     assert abs(g - go) <= 2e-6 * max(1.0, abs(go)), (g, go)
     print(f"{name}: nnz {inst.nnz} x err {xerr.max():.2e} grad rel {rel:.2e} dual rel {abs(g - go) / abs(go):.2e}")
 
