@@ -17,7 +17,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdualip.so")
+LIB_PATH = os.environ.get("DUALIP_LIB", os.path.join(HERE, "libdualip.so"))
 
 DL_OK, DL_NOT_CONVERGED = 0, 1
 STATUS = {0: "DL_OK", 1: "DL_NOT_CONVERGED", -1: "DL_EINVAL", -2: "DL_ENOMEM", -3: "DL_EHIP",

@@ -46,6 +46,15 @@ constexpr int DL_MAX_BUCKETS = 8;
 constexpr int DL_LONG = 7;               // bucket code of rows longer than 64*KMAX
 constexpr int DL_MAX_MJ = 13000;         // m*J that fits the LDS accumulation (12 B per entry)
 constexpr int DL_MAX_FAMILIES = 4;
+// Elements per lane in the group path: families with a == 1 only, and with a stored.
+#ifndef DL_KMAX_PLAIN
+#define DL_KMAX_PLAIN 12
+#endif
+constexpr int DL_KMAX_A = 8;
+// Elements of zero padding after idx, c and every stored a family: a group of
+// lanes may read up to 64*KMAX + 63 elements past a row start without
+// predication, and masks what lies past the row.
+constexpr int64_t DL_PAD = 4096;
 
 // A degree bucket: users [user_begin, user_end) of the reordered problem (sorted
 // by degree, longest first) served by groups of 2^glog lanes, 64/2^glog users
@@ -64,6 +73,7 @@ enum : int {
   M_OBJ = 2,     // accumulate the per-user Lagrangian terms (FP64 per workgroup)
   M_REPAIR = 4,  // accumulate c.x~ + gamma/2 x~^2 with x~ = r_j x (certificate)
   M_VIN = 8,     // v given in caller order (ProjectionMap), no gather
+  M_XOUT = 16,   // write x in the caller's order
 };
 
 struct dl_grad_args {
@@ -74,6 +84,7 @@ struct dl_grad_args {
   const void* aval;        // n_stored * nnz
   const int64_t* orig_rp;  // per reordered user: row start in the caller's order
   int64_t nnz;
+  int64_t astride;         // elements between stored a families (nnz + DL_PAD)
   int32_t J, m;
   int32_t a_slot[DL_MAX_FAMILIES];  // stored slot of family k, -1: a == 1
   float qscale[DL_MAX_FAMILIES];    // fixed-point scale of family k

@@ -9,12 +9,18 @@
 //  * each workgroup (1024 lanes, one per CU) stages lam (m*J FP32) in LDS once
 //    and gathers from there;
 //  * users are reordered by degree, longest first, and served by groups of
-//    2^glog lanes holding up to KMAX elements each in registers (lane, group or
-//    whole-wavefront per user); rows longer than 64*KMAX loop over the row;
-//  * the projection finds the simplex threshold by Newton steps from below on
-//    f(theta) = sum max(v - theta, 0) - z (each step is the exact threshold of
-//    the current active set, so it stops when the set stops shrinking), with
-//    the paper's early exit when the positive part already fits;
+//    G = 2^glog lanes holding up to KMAX elements each in registers; G is a
+//    compile-time constant per degree bucket so every load of a row uses an
+//    immediate offset, and the arrays carry zero padding so loads past a row
+//    end need no predication (masked by select); rows longer than 64*KMAX use
+//    a wavefront-wide loop over the row;
+//  * each wavefront prefetches the next task's row pointers and row data while
+//    it computes the current task (software pipelining);
+//  * the simplex threshold: the paper's early exit when the positive part
+//    already fits, an exact exit when the largest entry leads the second by at
+//    least z, otherwise Newton steps from below on f(theta) = sum max(v-theta,0)
+//    - z (each step is the exact threshold of the current active set; the pass
+//    that forms it also checks whether the set survives the step);
 //  * a_k * x is rounded to a per-family fixed-point grid and added with 64-bit
 //    integer LDS atomics into a per-workgroup histogram over items; integer
 //    addition is associative, so the sums are bitwise reproducible for any
@@ -36,36 +42,76 @@ __device__ __forceinline__ float swz_xor16(float v) {
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
 }
 
-struct OpSum {
-  __device__ __forceinline__ float operator()(float a, float b) const { return a + b; }
-};
-struct OpMax {
-  __device__ __forceinline__ float operator()(float a, float b) const { return fmaxf(a, b); }
-};
+// One butterfly step of an all-reduce over aligned groups of 2^(STEP+1) lanes.
+template <int STEP>
+__device__ __forceinline__ float xstep(float v) {
+  if constexpr (STEP == 0) return dpp_f<0xB1>(v);   // quad_perm(1,0,3,2): lane ^ 1
+  if constexpr (STEP == 1) return dpp_f<0x4E>(v);   // quad_perm(2,3,0,1): lane ^ 2
+  if constexpr (STEP == 2) return dpp_f<0x141>(v);  // row_half_mirror: pairs the two quads of 8
+  if constexpr (STEP == 3) return dpp_f<0x140>(v);  // row_mirror: pairs the two halves of 16
+  if constexpr (STEP == 4) return swz_xor16(v);
+  return __shfl_xor(v, 32, 64);
+}
 
-// All-reduce over aligned groups of 2^glog lanes.  Every lane of a group ends
-// with the same bits (each combining step adds the same two operands).
-template <typename Op>
-__device__ __forceinline__ float group_allreduce(float v, int glog, Op op) {
-  if (glog > 0) v = op(v, dpp_f<0xB1>(v));   // quad_perm(1,0,3,2): lane ^ 1
-  if (glog > 1) v = op(v, dpp_f<0x4E>(v));   // quad_perm(2,3,0,1): lane ^ 2
-  if (glog > 2) v = op(v, dpp_f<0x141>(v));  // row_half_mirror: pairs the two quads of 8
-  if (glog > 3) v = op(v, dpp_f<0x140>(v));  // row_mirror: pairs the two halves of 16
-  if (glog > 4) v = op(v, swz_xor16(v));
-  if (glog > 5) v = op(v, __shfl_xor(v, 32, 64));
+// All-reduce (sum / max / min) over aligned groups of 2^GLOG lanes.  Every lane
+// of a group ends with the same bits (each step combines the same two operands).
+template <int GLOG>
+__device__ __forceinline__ float gsum(float v) {
+  if constexpr (GLOG > 0) v += xstep<0>(v);
+  if constexpr (GLOG > 1) v += xstep<1>(v);
+  if constexpr (GLOG > 2) v += xstep<2>(v);
+  if constexpr (GLOG > 3) v += xstep<3>(v);
+  if constexpr (GLOG > 4) v += xstep<4>(v);
+  if constexpr (GLOG > 5) v += xstep<5>(v);
   return v;
+}
+template <int GLOG>
+__device__ __forceinline__ float gmax(float v) {
+  if constexpr (GLOG > 0) v = fmaxf(v, xstep<0>(v));
+  if constexpr (GLOG > 1) v = fmaxf(v, xstep<1>(v));
+  if constexpr (GLOG > 2) v = fmaxf(v, xstep<2>(v));
+  if constexpr (GLOG > 3) v = fmaxf(v, xstep<3>(v));
+  if constexpr (GLOG > 4) v = fmaxf(v, xstep<4>(v));
+  if constexpr (GLOG > 5) v = fmaxf(v, xstep<5>(v));
+  return v;
+}
+template <int GLOG>
+__device__ __forceinline__ float gmin(float v) {
+  if constexpr (GLOG > 0) v = fminf(v, xstep<0>(v));
+  if constexpr (GLOG > 1) v = fminf(v, xstep<1>(v));
+  if constexpr (GLOG > 2) v = fminf(v, xstep<2>(v));
+  if constexpr (GLOG > 3) v = fminf(v, xstep<3>(v));
+  if constexpr (GLOG > 4) v = fminf(v, xstep<4>(v));
+  if constexpr (GLOG > 5) v = fminf(v, xstep<5>(v));
+  return v;
+}
+// (largest, second largest) over the group
+template <int STEP>
+__device__ __forceinline__ void top2_step(float& m1, float& m2) {
+  const float o1 = xstep<STEP>(m1), o2 = xstep<STEP>(m2);
+  const float hi = fmaxf(m1, o1), lo = fminf(m1, o1);
+  m2 = fmaxf(lo, fmaxf(m2, o2));
+  m1 = hi;
+}
+template <int GLOG>
+__device__ __forceinline__ void gtop2(float& m1, float& m2) {
+  if constexpr (GLOG > 0) top2_step<0>(m1, m2);
+  if constexpr (GLOG > 1) top2_step<1>(m1, m2);
+  if constexpr (GLOG > 2) top2_step<2>(m1, m2);
+  if constexpr (GLOG > 3) top2_step<3>(m1, m2);
+  if constexpr (GLOG > 4) top2_step<4>(m1, m2);
+  if constexpr (GLOG > 5) top2_step<5>(m1, m2);
 }
 
 template <typename TV>
-__device__ __forceinline__ float load_val(const void* base, int64_t e);
+__device__ __forceinline__ float ldv(const TV* p);
 template <>
-__device__ __forceinline__ float load_val<float>(const void* base, int64_t e) {
-  return __builtin_nontemporal_load(reinterpret_cast<const float*>(base) + e);
+__device__ __forceinline__ float ldv<float>(const float* p) {
+  return *p;
 }
 template <>
-__device__ __forceinline__ float load_val<uint16_t>(const void* base, int64_t e) {
-  uint32_t h = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(base) + e);
-  return __uint_as_float(h << 16);
+__device__ __forceinline__ float ldv<uint16_t>(const uint16_t* p) {
+  return __uint_as_float((uint32_t)(*p) << 16);
 }
 
 __device__ __forceinline__ void hist_add(unsigned long long* h, int r, float w, float qs) {
@@ -73,169 +119,288 @@ __device__ __forceinline__ void hist_add(unsigned long long* h, int r, float w, 
   if (q != 0) atomicAdd(h + r, (unsigned long long)(long long)q);
 }
 
-// Threshold of the simplex projection for one group, given v in registers.
-// Returns theta; the projection is max(v - theta, 0).  Lanes of invalid groups
-// (no user) carry only -inf and return 0.
-template <int KMAX>
-__device__ __forceinline__ float simplex_theta(const float (&v)[KMAX], int K, int glog, float z, bool eq) {
-  float vmax = -INFINITY, sp = 0.f, cp = 0.f;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < K) {
-      vmax = fmaxf(vmax, v[k]);
-      float p = fmaxf(v[k], 0.f);
-      sp += p;
-      cp += (v[k] > 0.f) ? 1.f : 0.f;
-    }
+// ---------------------------------------------------------------------------
+// Group path: 2^GLOG lanes per user, up to KMAX elements per lane.
+// ---------------------------------------------------------------------------
+// Per-lane element loops run in chunks of 4: a chunk runs when its first
+// element is below the task's K (uniform), elements past the row end inside a
+// chunk are masked.  Whole chunks let the compiler batch loads and LDS reads.
+#define DL_FOR_K(k, KMAX, K)                                   \
+  _Pragma("unroll") for (int kc_ = 0; kc_ < (KMAX); kc_ += 4)  \
+    if (kc_ < (K))                                             \
+      _Pragma("unroll") for (int k = kc_; k < kc_ + 4; ++k)
+
+struct TaskMeta {
+  int64_t s;   // row start (0 for lanes without a user)
+  int64_t e;   // row end (0 for lanes without a user); the length is taken late so
+               // the row-pointer load is not waited on where it is issued
+  int64_t os;  // row start in the caller's order
+};
+
+template <int GLOG>
+__device__ __forceinline__ TaskMeta load_meta(const dl_grad_args& A, const dl_bucket& B, int64_t t, int lane,
+                                              bool need_os) {
+  const int64_t u = B.user_begin + (t - B.task_begin) * (int64_t)(64 >> GLOG) + (lane >> GLOG);
+  TaskMeta m;
+  m.s = 0;
+  m.e = 0;
+  m.os = 0;
+  if (u < B.user_end) {
+    m.s = A.rp[u];
+    m.e = A.rp[u + 1];
+    if (need_os) m.os = A.orig_rp[u];
   }
-  vmax = group_allreduce(vmax, glog, OpMax());
-  sp = group_allreduce(sp, glog, OpSum());
-  cp = group_allreduce(cp, glog, OpSum());
-  float theta = 0.f;
-  bool done;
-  if (vmax == -INFINITY) {
-    done = true;                           // no user in this group
-  } else if (!eq && sp <= z) {
-    done = true;                           // positive part already in the simplex
-  } else {
-    done = false;
-    theta = vmax - z;                      // f(vmax - z) >= 0: a point left of the root
-    if (sp > z && cp > 0.f) theta = fmaxf(theta, (sp - z) / cp);  // Newton step from 0
-  }
-  float prev = -1.f;
-  for (int it = 0; it < 64 && __any(!done); ++it) {
-    float f = 0.f, cnt = 0.f;
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      if (k < K) {
-        float t = v[k] - theta;
-        f += fmaxf(t, 0.f);
-        cnt += (t > 0.f) ? 1.f : 0.f;
-      }
-    }
-    f = group_allreduce(f, glog, OpSum());
-    cnt = group_allreduce(cnt, glog, OpSum());
-    if (!done) {
-      // Newton step: exact threshold of the active set {v > theta}
-      float nt = theta + (f - z) / cnt;
-      bool stable = (cnt == prev) || (fabsf(f - z) <= z * 0x1p-22f);
-      theta = nt;
-      prev = cnt;
-      done = stable;
-    }
-  }
-  return theta;
+  return m;
 }
 
-template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__device__ __forceinline__ void group_task(const dl_grad_args& A, int64_t t, const dl_bucket& B,
-                                           const float* s_mu, const float* s_rf, unsigned long long* s_hist,
-                                           int lane, double& acc) {
-  const int glog = B.glog;
-  const int g = 1 << glog;
-  const int64_t u_first = B.user_begin + (t - B.task_begin) * (int64_t)(64 >> glog);
-  const int grp = lane >> glog;
-  const int lid = lane & (g - 1);
-  const int64_t u = u_first + grp;
-  const bool valid = u < B.user_end;
-  int64_t s = 0;
-  int d = 0;
-  if (valid) {
-    s = A.rp[u];
-    d = (int)(A.rp[u + 1] - s);
-  }
-  // users are sorted longest first: lane 0 holds the longest row of the task
-  const int d0 = __builtin_amdgcn_readfirstlane(d);
-  const int K = (d0 + g - 1) >> glog;
-  const int64_t os = ((MODE & M_VIN) || A.x_out) && valid ? A.orig_rp[u] : 0;
+template <int MF, bool HAS_A, int KMAX>
+struct RowRegs {
+  int j[KMAX];
+  float c[KMAX];  // c, replaced in place by v
+  float a[HAS_A ? MF : 1][KMAX];
+};
 
-  float v[KMAX];
-  int jj[KMAX];
-  float cc[KMAX];
-  float aa[HAS_A ? MF : 1][KMAX];
+// Issues the loads of one task's rows (lane element e = lid + k*G, k < K).
+// Reads past a row end stay inside the padded arrays and are masked later.
+template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
+__device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
+                                          RowRegs<MF, HAS_A, KMAX>& R) {
+  constexpr int G = 1 << GLOG;
+  K = __builtin_amdgcn_readfirstlane(K);
+  if constexpr ((MODE & M_VIN) != 0) {
+    const int d = (int)(m.e - m.s);
+    const float* vp = A.v_in + m.os + lid;
+    DL_FOR_K(k, KMAX, K) R.c[k] = (lid + k * G < d) ? vp[k * G] : 0.f;
+    return;
+  }
+  const int32_t* ip = A.idx + m.s + lid;
+  const TV* cp = reinterpret_cast<const TV*>(A.cval) + m.s + lid;
+  DL_FOR_K(k, KMAX, K) {
+    R.j[k] = ip[k * G];
+    R.c[k] = ldv<TV>(cp + k * G);
+  }
+  if constexpr (HAS_A) {
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    v[k] = -INFINITY;
-    jj[k] = 0;
-    cc[k] = 0.f;
-    if (k < K) {
-      const int e = lid + (k << glog);
-      if (e < d) {
-        if (MODE & M_VIN) {
-          v[k] = A.v_in[os + e];
-        } else {
-          const int j = A.idx[s + e];
-          jj[k] = j;
-          const float c = load_val<TV>(A.cval, s + e);
-          float sdot = 0.f;
+    for (int f = 0; f < MF; ++f) {
+      if (f < A.m && A.a_slot[f] >= 0) {
+        const TV* ap = reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + m.s + lid;
+        DL_FOR_K(k, KMAX, K) R.a[f][k] = ldv<TV>(ap + k * G);
+      }
+    }
+  }
+}
+
+// v = (c + sum_k a_k mu_k[j]) * (-1/gamma) in place of c; -inf past the row end.
+template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
+__device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
+                                         RowRegs<MF, HAS_A, KMAX>& R, const float* s_mu,
+                                         float (&cc)[(MODE & M_REPAIR) ? KMAX : 1]) {
+  constexpr int G = 1 << GLOG;
+  K = __builtin_amdgcn_readfirstlane(K);
+  const int d = (int)(m.e - m.s);
+  DL_FOR_K(k, KMAX, K) {
+    {
+      const bool in = lid + k * G < d;
+      float val;
+      if constexpr ((MODE & M_VIN) != 0) {
+        val = R.c[k];
+      } else {
+        const int j = R.j[k];
+        float sdot = 0.f;
 #pragma unroll
-          for (int f = 0; f < MF; ++f) {
-            if (f < A.m) {
-              float af = 1.f;
-              if (HAS_A && A.a_slot[f] >= 0) {
-                af = load_val<TV>(A.aval, (int64_t)A.a_slot[f] * A.nnz + s + e);
-              }
-              if (HAS_A) aa[f][k] = af;
-              sdot = fmaf(af, s_mu[f * A.J + j], sdot);
+        for (int f = 0; f < MF; ++f) {
+          if (f < A.m) {
+            float af = 1.f;
+            if constexpr (HAS_A) {
+              if (A.a_slot[f] >= 0) af = R.a[f][k];
             }
+            sdot = fmaf(af, s_mu[f * A.J + j], sdot);
           }
-          cc[k] = c;
-          v[k] = (c + sdot) * A.neg_inv_gamma;  // eq. 3 argument
         }
+        if constexpr ((MODE & M_REPAIR) != 0) cc[k] = R.c[k];
+        val = (R.c[k] + sdot) * A.neg_inv_gamma;  // eq. 3 argument
+      }
+      R.c[k] = in ? val : -INFINITY;
+    }
+  }
+}
+
+// Projects the task's rows (v in R.c) and accumulates what MODE asks.
+template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
+__device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
+                                             RowRegs<MF, HAS_A, KMAX>& R, const float* s_rf,
+                                             unsigned long long* s_hist, double& acc,
+                                             const float (&cc)[(MODE & M_REPAIR) ? KMAX : 1]) {
+  constexpr int G = 1 << GLOG;
+  K = __builtin_amdgcn_readfirstlane(K);
+  float (&v)[KMAX] = R.c;
+  const float z = A.radius;
+  const bool box = (A.proj == DL_PROJ_BOX);
+  float theta = 0.f;
+  if (!box) {
+    // pass A: largest two entries, positive part and its count
+    float m1 = -INFINITY, m2 = -INFINITY, sp = 0.f, cp = 0.f;
+    DL_FOR_K(k, KMAX, K) {
+      {
+        m2 = fmaxf(m2, fminf(m1, v[k]));
+        m1 = fmaxf(m1, v[k]);
+        sp += fmaxf(v[k], 0.f);
+        cp += v[k] > 0.f ? 1.f : 0.f;
+      }
+    }
+    gtop2<GLOG>(m1, m2);
+    sp = gsum<GLOG>(sp);
+    cp = gsum<GLOG>(cp);
+    const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
+    bool done;
+    if (m1 == -INFINITY || (!eq && sp <= z)) {
+      done = true;                       // no user here, or the positive part already fits
+    } else if (m1 - m2 >= z) {
+      theta = m1 - z;                    // the leader alone carries mass z
+      done = true;
+    } else {
+      theta = m1 - z;                    // f(m1 - z) >= 0: left of the root
+      if (sp > z) theta = fmaxf(theta, (sp - z) * __builtin_amdgcn_rcpf(cp));  // Newton step from 0
+      done = false;
+    }
+    for (int it = 0; it < 64 && __any(!done); ++it) {
+      float f = 0.f, cnt = 0.f, mina = INFINITY;
+      DL_FOR_K(k, KMAX, K) {
+        {
+          const float t = v[k] - theta;
+          f += fmaxf(t, 0.f);
+          const bool act = t > 0.f;
+          cnt += act ? 1.f : 0.f;
+          mina = fminf(mina, act ? v[k] : INFINITY);
+        }
+      }
+      f = gsum<GLOG>(f);
+      cnt = gsum<GLOG>(cnt);
+      mina = gmin<GLOG>(mina);
+      if (!done) {
+        // Newton step: the exact threshold of the active set {v > theta}; the
+        // set survives the step when its smallest member stays above it
+        const float nt = theta + (f - z) * __builtin_amdgcn_rcpf(cnt);
+        done = (mina > nt) || (fabsf(f - z) <= z * 0x1p-22f);
+        theta = nt;
       }
     }
   }
 
-  const float z = A.radius;
-  float theta = 0.f;
-  const bool box = (A.proj == DL_PROJ_BOX);
-  if (!box) theta = simplex_theta<KMAX>(v, K, glog, z, A.proj == DL_PROJ_SIMPLEX_EQ);
-
   float lobj = 0.f;
+  DL_FOR_K(k, KMAX, K) {
+    {
+      const float x = box ? fminf(fmaxf(v[k], 0.f), z) : fmaxf(v[k] - theta, 0.f);
+      if constexpr ((MODE & M_XOUT) != 0) {
+        if (lid + k * G < (int)(m.e - m.s)) A.x_out[m.os + lid + k * G] = x;
+      }
+      if constexpr ((MODE & M_HIST) != 0) {
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < K) {
-      const int e = lid + (k << glog);
-      if (e < d) {
-        float x = box ? fminf(fmaxf(v[k], 0.f), z) : fmaxf(v[k] - theta, 0.f);
-        if (A.x_out) A.x_out[os + e] = x;
-        if (MODE & M_HIST) {
-#pragma unroll
-          for (int f = 0; f < MF; ++f) {
-            if (f < A.m) {
-              float w = (HAS_A && A.a_slot[f] >= 0) ? aa[HAS_A ? f : 0][k] * x : x;
-              hist_add(s_hist, f * A.J + jj[k], w, A.qscale[f]);
+        for (int f = 0; f < MF; ++f) {
+          if (f < A.m) {
+            float w = x;
+            if constexpr (HAS_A) {
+              if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
             }
+            hist_add(s_hist, f * A.J + R.j[k], w, A.qscale[f]);
           }
         }
-        if (MODE & M_OBJ) {
-          // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v
-          lobj += x * fmaf(0.5f * A.gamma, x, -A.gamma * v[k]);
-        }
-        if (MODE & M_REPAIR) {
-          const float xt = s_rf[jj[k]] * x;
-          lobj += xt * fmaf(0.5f * A.gamma, xt, cc[k]);
-        }
+      }
+      if constexpr ((MODE & M_OBJ) != 0) {
+        // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
+        lobj += x * fmaf(0.5f * A.gamma, x, -A.gamma * fmaxf(v[k], -3.0e38f));
+      }
+      if constexpr ((MODE & M_REPAIR) != 0) {
+        const float xt = s_rf[R.j[k]] * x;
+        lobj += xt * fmaf(0.5f * A.gamma, xt, cc[k]);
       }
     }
   }
   if (MODE & (M_OBJ | M_REPAIR)) acc += (double)lobj;
 }
 
+// The tasks t0, t0 + DL_WAVES, ... < t1 of one bucket.  With PF the next
+// task's rows load while the current one is projected: gather (waits for this
+// task's rows), issue the next task's loads, then project and accumulate.
+template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
+__device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucket& B, int64_t t0, int64_t t1,
+                                           int lane, const float* s_mu, const float* s_rf,
+                                           unsigned long long* s_hist, double& acc) {
+  if (t0 >= t1) return;
+  // keeps per-bucket lane arithmetic inside this bucket's code (otherwise it is
+  // hoisted out of the kernel's bucket loop for every bucket at once and spills)
+  asm volatile("" : "+v"(lane));
+  constexpr bool PF = (MF == 1) && !(MODE & M_REPAIR);
+  constexpr int G = 1 << GLOG;
+  const int lid = lane & (G - 1);
+  constexpr bool need_os = (MODE & (M_VIN | M_XOUT)) != 0;
+  auto kof = [&](const TaskMeta& m) {
+    // users are sorted longest first: lane 0 holds the task's longest row
+    const int d0 = __builtin_amdgcn_readfirstlane((int)(m.e - m.s));
+    return (d0 + G - 1) >> GLOG;
+  };
+  float cc[(MODE & M_REPAIR) ? KMAX : 1];
+  if constexpr (!PF) {
+    RowRegs<MF, HAS_A, KMAX> R;
+    for (int64_t t = t0; t < t1; t += DL_WAVES) {
+      TaskMeta m = load_meta<GLOG>(A, B, t, lane, need_os);
+      const int K = kof(m);
+      load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R);
+      gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R, s_mu, cc);
+      project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R, s_rf, s_hist, acc, cc);
+    }
+    return;
+  }
+  RowRegs<MF, HAS_A, KMAX> RA, RB;
+  TaskMeta ma = load_meta<GLOG>(A, B, t0, lane, need_os);
+  TaskMeta mb = ma;
+  int64_t t = t0;
+  if (t + DL_WAVES < t1) mb = load_meta<GLOG>(A, B, t + DL_WAVES, lane, need_os);
+  int ka = kof(ma), kb = 0;
+  load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA);
+  while (true) {
+    gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA, s_mu, cc);
+    TaskMeta mc = mb;
+    if (t + DL_WAVES < t1) {
+      kb = kof(mb);
+      load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB);
+      if (t + 2 * DL_WAVES < t1) mc = load_meta<GLOG>(A, B, t + 2 * DL_WAVES, lane, need_os);
+    }
+    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA, s_rf, s_hist, acc, cc);
+    t += DL_WAVES;
+    if (t >= t1) break;
+    gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB, s_mu, cc);
+    TaskMeta md = mc;
+    if (t + DL_WAVES < t1) {
+      ka = kof(mc);
+      load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mc, ka, lid, RA);
+      if (t + 2 * DL_WAVES < t1) md = load_meta<GLOG>(A, B, t + 2 * DL_WAVES, lane, need_os);
+    }
+    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB, s_rf, s_hist, acc, cc);
+    t += DL_WAVES;
+    if (t >= t1) break;
+    ma = mc;
+    mb = md;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Rows longer than 64*KMAX: one wavefront per user, re-reading the row per
 // Newton step (the row stays in L1/L2, so HBM sees it once).
+// ---------------------------------------------------------------------------
 template <int MF, bool HAS_A, typename TV, int MODE>
 __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu, int64_t s, int64_t os, int e,
                                         int& j, float& c, float (&af)[HAS_A ? MF : 1]) {
-  if (MODE & M_VIN) return A.v_in[os + e];
+  if constexpr ((MODE & M_VIN) != 0) return A.v_in[os + e];
   j = A.idx[s + e];
-  c = load_val<TV>(A.cval, s + e);
+  c = ldv<TV>(reinterpret_cast<const TV*>(A.cval) + s + e);
   float sdot = 0.f;
 #pragma unroll
   for (int f = 0; f < MF; ++f) {
     if (f < A.m) {
       float a = 1.f;
-      if (HAS_A && A.a_slot[f] >= 0) a = load_val<TV>(A.aval, (int64_t)A.a_slot[f] * A.nnz + s + e);
+      if (HAS_A && A.a_slot[f] >= 0)
+        a = ldv<TV>(reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + s + e);
       if (HAS_A) af[f] = a;
       sdot = fmaf(a, s_mu[f * A.J + j], sdot);
     }
@@ -245,15 +410,15 @@ __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu
 
 template <int MF, bool HAS_A, typename TV, int MODE>
 __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, const dl_bucket& B, const float* s_mu,
-                                       const float* s_rf, unsigned long long* s_hist, int lane, double& acc) {
+                                          const float* s_rf, unsigned long long* s_hist, int lane, double& acc) {
   const int64_t u = B.user_begin + (t - B.task_begin);
   const int64_t s = A.rp[u];
   const int d = (int)(A.rp[u + 1] - s);
-  const int64_t os = ((MODE & M_VIN) || A.x_out) ? A.orig_rp[u] : 0;
+  const int64_t os = (MODE & (M_VIN | M_XOUT)) ? A.orig_rp[u] : 0;
   const float z = A.radius;
   const bool box = (A.proj == DL_PROJ_BOX);
-  int j;
-  float c;
+  int j = 0;
+  float c = 0.f;
   float af[HAS_A ? MF : 1];
   float theta = 0.f;
   if (!box) {
@@ -264,28 +429,28 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
       sp += fmaxf(v, 0.f);
       cp += v > 0.f ? 1.f : 0.f;
     }
-    vmax = group_allreduce(vmax, 6, OpMax());
-    sp = group_allreduce(sp, 6, OpSum());
-    cp = group_allreduce(cp, 6, OpSum());
+    vmax = gmax<6>(vmax);
+    sp = gsum<6>(sp);
+    cp = gsum<6>(cp);
     const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
     if (eq || sp > z) {
       theta = vmax - z;
       if (sp > z && cp > 0.f) theta = fmaxf(theta, (sp - z) / cp);
-      float prev = -1.f;
       for (int it = 0; it < 64; ++it) {
-        float f = 0.f, cnt = 0.f;
+        float f = 0.f, cnt = 0.f, mina = INFINITY;
         for (int e = lane; e < d; e += 64) {
           float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
           float tt = v - theta;
           f += fmaxf(tt, 0.f);
           cnt += tt > 0.f ? 1.f : 0.f;
+          mina = fminf(mina, tt > 0.f ? v : INFINITY);
         }
-        f = group_allreduce(f, 6, OpSum());
-        cnt = group_allreduce(cnt, 6, OpSum());
-        float nt = theta + (f - z) / cnt;
-        bool stable = (cnt == prev) || (fabsf(f - z) <= z * 0x1p-22f);
+        f = gsum<6>(f);
+        cnt = gsum<6>(cnt);
+        mina = gmin<6>(mina);
+        const float nt = theta + (f - z) / cnt;
+        const bool stable = (mina > nt) || (fabsf(f - z) <= z * 0x1p-22f);
         theta = nt;
-        prev = cnt;
         if (stable) break;
       }
     }
@@ -294,8 +459,8 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
   for (int e = lane; e < d; e += 64) {
     float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
     float x = box ? fminf(fmaxf(v, 0.f), z) : fmaxf(v - theta, 0.f);
-    if (A.x_out) A.x_out[os + e] = x;
-    if (MODE & M_HIST) {
+    if constexpr ((MODE & M_XOUT) != 0) A.x_out[os + e] = x;
+    if constexpr ((MODE & M_HIST) != 0) {
 #pragma unroll
       for (int f = 0; f < MF; ++f) {
         if (f < A.m) {
@@ -304,8 +469,8 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
         }
       }
     }
-    if (MODE & M_OBJ) lobj += x * fmaf(0.5f * A.gamma, x, -A.gamma * v);
-    if (MODE & M_REPAIR) {
+    if constexpr ((MODE & M_OBJ) != 0) lobj += x * fmaf(0.5f * A.gamma, x, -A.gamma * v);
+    if constexpr ((MODE & M_REPAIR) != 0) {
       const float xt = s_rf[j] * x;
       lobj += xt * fmaf(0.5f * A.gamma, xt, c);
     }
@@ -335,17 +500,30 @@ __global__ void __launch_bounds__(DL_WG) grad_pass(dl_grad_args A) {
 
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  const int64_t t0 = A.wg_task[blockIdx.x];
-  const int64_t t1 = A.wg_task[blockIdx.x + 1];
+  const int64_t w0 = A.wg_task[blockIdx.x];
+  const int64_t w1 = A.wg_task[blockIdx.x + 1];
   double acc = 0.0;
-  int b = 0;
-  for (int64_t t = t0 + wave; t < t1; t += DL_WAVES) {
-    while (b + 1 < A.n_buckets && t >= A.bk[b + 1].task_begin) ++b;
+  for (int b = 0; b < A.n_buckets; ++b) {
     const dl_bucket& B = A.bk[b];
-    if (B.glog == DL_LONG) {
-      long_task<MF, HAS_A, TV, MODE>(A, t, B, s_mu, s_rf, s_hist, lane, acc);
-    } else {
-      group_task<MF, HAS_A, KMAX, TV, MODE>(A, t, B, s_mu, s_rf, s_hist, lane, acc);
+    const int64_t b1 = (b + 1 < A.n_buckets) ? A.bk[b + 1].task_begin : w1;
+    const int64_t lo = w0 > B.task_begin ? w0 : B.task_begin;
+    const int64_t hi = w1 < b1 ? w1 : b1;
+    if (lo >= hi) continue;
+    // this wavefront's tasks: w0 + wave + k*DL_WAVES inside [lo, hi)
+    int64_t first = w0 + wave;
+    if (first < lo) first += ((lo - first + DL_WAVES - 1) / DL_WAVES) * DL_WAVES;
+    switch (B.glog) {
+      case 0: run_bucket<0, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      case 1: run_bucket<1, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      case 2: run_bucket<2, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      case 3: run_bucket<3, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      case 4: run_bucket<4, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      case 5: run_bucket<5, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      case 6: run_bucket<6, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      default:
+        for (int64_t t = first; t < hi; t += DL_WAVES)
+          long_task<MF, HAS_A, TV, MODE>(A, t, B, s_mu, s_rf, s_hist, lane, acc);
+        break;
     }
   }
   if (MODE & (M_OBJ | M_REPAIR)) {
@@ -377,8 +555,10 @@ dl_status launch_mode(const dl_problem* P, int mode, const dl_grad_args& A, size
   switch (mode) {
     case M_HIST: return launch_one<MF, HAS_A, KMAX, TV, M_HIST>(P, A, lds);
     case M_HIST | M_OBJ: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ>(P, A, lds);
+    case M_HIST | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT>(P, A, lds);
+    case M_HIST | M_OBJ | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT>(P, A, lds);
     case M_REPAIR: return launch_one<MF, HAS_A, KMAX, TV, M_REPAIR>(P, A, lds);
-    case M_VIN: return launch_one<MF, HAS_A, KMAX, TV, M_VIN>(P, A, lds);
+    case M_VIN | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_VIN | M_XOUT>(P, A, lds);
     default: dl_set_error("internal: unknown gradient-pass mode"); return DL_EINVAL;
   }
 }
@@ -398,7 +578,9 @@ void set_attr_all() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_REPAIR>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_VIN>,
+  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
@@ -415,14 +597,14 @@ size_t dl_grad_lds_bytes(const dl_problem* P, int mode) {
 
 dl_status dl_grad_prepare(const dl_problem* P) {
   if (P->mf == 1 && !P->has_a) {
-    set_attr_all<1, false, 16, float>();
-    set_attr_all<1, false, 16, uint16_t>();
+    set_attr_all<1, false, DL_KMAX_PLAIN, float>();
+    set_attr_all<1, false, DL_KMAX_PLAIN, uint16_t>();
   } else if (P->mf == 1) {
-    set_attr_all<1, true, 16, float>();
-    set_attr_all<1, true, 16, uint16_t>();
+    set_attr_all<1, true, DL_KMAX_A, float>();
+    set_attr_all<1, true, DL_KMAX_A, uint16_t>();
   } else {
-    set_attr_all<4, true, 8, float>();
-    set_attr_all<4, true, 8, uint16_t>();
+    set_attr_all<4, true, DL_KMAX_A, float>();
+    set_attr_all<4, true, DL_KMAX_A, uint16_t>();
   }
   return DL_OK;
 }
@@ -430,6 +612,7 @@ dl_status dl_grad_prepare(const dl_problem* P) {
 dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double gamma, const float* rfac,
                          const float* v_in, float* x_out, double* obj_part) {
   if (P->n_wg <= 0) return DL_OK;
+  if (x_out) mode |= M_XOUT;
   dl_grad_args A;
   memset(&A, 0, sizeof(A));
   A.rp = P->rp;
@@ -438,6 +621,7 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
   A.aval = P->aval;
   A.orig_rp = P->orig_rp;
   A.nnz = P->nnz;
+  A.astride = P->nnz + DL_PAD;
   A.J = P->J;
   A.m = P->m;
   for (int k = 0; k < DL_MAX_FAMILIES; ++k) {
@@ -458,7 +642,7 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
   A.obj_part = obj_part;
   A.x_out = x_out;
   const size_t lds = dl_grad_lds_bytes(P, mode);
-  if (P->mf == 1 && !P->has_a) return launch_storage<1, false, 16>(P, mode, A, lds);
-  if (P->mf == 1) return launch_storage<1, true, 16>(P, mode, A, lds);
-  return launch_storage<4, true, 8>(P, mode, A, lds);
+  if (P->mf == 1 && !P->has_a) return launch_storage<1, false, DL_KMAX_PLAIN>(P, mode, A, lds);
+  if (P->mf == 1) return launch_storage<1, true, DL_KMAX_A>(P, mode, A, lds);
+  return launch_storage<4, true, DL_KMAX_A>(P, mode, A, lds);
 }

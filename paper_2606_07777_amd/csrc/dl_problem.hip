@@ -68,7 +68,7 @@ __global__ void gather_rows(const int64_t* orig_rp, const int64_t* new_rp, int64
     else reinterpret_cast<float*>(c_out)[ns + e] = cv;
     for (int sl = 0; sl < n_stored; ++sl) {
       float av = a_in[(int64_t)fam_of_slot[sl] * nnz + os + e];
-      int64_t dst = (int64_t)sl * nnz + ns + e;
+      int64_t dst = (int64_t)sl * (nnz + DL_PAD) + ns + e;
       if (bf16) reinterpret_cast<uint16_t*>(a_out)[dst] = dl_f32_to_bf16_rne(av);
       else reinterpret_cast<float*>(a_out)[dst] = av;
     }
@@ -96,10 +96,10 @@ __global__ void item_stats(const int32_t* idx, const void* aval, int64_t nnz, in
     const int32_t j = idx[e];
     atomicAdd(cnt + j, 1ull);
     for (int k = 0; k < m; ++k) {
-      double ak = slot[k] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[k] * nnz + e) : 1.0;
+      double ak = slot[k] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[k] * (nnz + DL_PAD) + e) : 1.0;
       for (int l = k; l < m; ++l) {
         if (slot[k] < 0 && slot[l] < 0) continue;  // 1*1: equals cnt
-        double al = slot[l] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[l] * nnz + e) : 1.0;
+        double al = slot[l] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[l] * (nnz + DL_PAD) + e) : 1.0;
         long long q = __double2ll_rn(ak * al * escale[k * m + l]);
         atomicAdd(M + ((int64_t)j * m + k) * m + l, (unsigned long long)q);
       }
@@ -176,9 +176,48 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   }
   P->I_active = I_active;
 
+  // ---- device validation of the caller's arrays ----
+  int* dflags = nullptr;
+  DL_HIP_TRY(hipMalloc((void**)&dflags, sizeof(int) * 16));
+  struct FreeGuard {
+    void* p;
+    ~FreeGuard() { if (p) (void)hipFree(p); }
+  } fg{dflags};
+  DL_HIP_TRY(hipMemsetAsync(dflags, 0, sizeof(int) * 16, st));
+  unsigned* d_amax = reinterpret_cast<unsigned*>(dflags + 4);
+  int* d_nonunit = dflags + 8;
+  if (I > 0) {
+    hipLaunchKernelGGL(validate_rows, dim3((unsigned)((I + 255) / 256)), dim3(256), 0, st, d->row_ptr, d->item_idx,
+                       d->c, d->a, I, J, m, nnz, dflags, d_amax, d_nonunit);
+    DL_HIP_TRY(hipGetLastError());
+  }
+  int hflags[16];
+  DL_HIP_TRY(hipMemcpyAsync(hflags, dflags, sizeof(hflags), hipMemcpyDeviceToHost, st));
+  DL_HIP_TRY(hipStreamSynchronize(st));
+  DL_CHECK_ARG(!(hflags[0] & F_RANGE), "item_idx out of range [0, n_items)");
+  DL_CHECK_ARG(!(hflags[0] & F_ORDER), "item_idx must be strictly increasing within each row");
+  DL_CHECK_ARG(!(hflags[0] & F_CNAN), "c has a non-finite entry");
+  DL_CHECK_ARG(!(hflags[0] & F_ANAN), "a has a non-finite entry");
+  float amax[DL_MAX_FAMILIES] = {1.f, 1.f, 1.f, 1.f};
+  int fam_of_slot[DL_MAX_FAMILIES] = {0, 0, 0, 0};
+  P->n_stored = 0;
+  for (int k = 0; k < m; ++k) {
+    if (d->a && hflags[8 + k]) {
+      P->a_slot[k] = P->n_stored;
+      fam_of_slot[P->n_stored++] = k;
+      float mx;
+      memcpy(&mx, &hflags[4 + k], 4);
+      amax[k] = mx;
+    } else {
+      P->a_slot[k] = -1;
+      amax[k] = 1.f;
+    }
+  }
+  P->has_a = P->n_stored > 0;
+
   // degree buckets: 2^glog lanes per user, at most kmax elements per lane
   P->mf = (m == 1) ? 1 : 4;
-  P->kmax = (m == 1) ? 16 : 8;
+  P->kmax = (m == 1 && !P->has_a) ? DL_KMAX_PLAIN : DL_KMAX_A;
   const int kmax = P->kmax;
   auto code_of = [&](int64_t dg) -> int {
     if (dg > 64 * (int64_t)kmax) return DL_LONG;
@@ -242,58 +281,23 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
     wg_task[(size_t)n_wg] = P->n_tasks;
   }
 
-  // ---- device validation of the caller's arrays ----
-  int* dflags = nullptr;
-  DL_HIP_TRY(hipMalloc((void**)&dflags, sizeof(int) * 16));
-  struct FreeGuard {
-    void* p;
-    ~FreeGuard() { if (p) (void)hipFree(p); }
-  } fg{dflags};
-  DL_HIP_TRY(hipMemsetAsync(dflags, 0, sizeof(int) * 16, st));
-  unsigned* d_amax = reinterpret_cast<unsigned*>(dflags + 4);
-  int* d_nonunit = dflags + 8;
-  if (I > 0) {
-    hipLaunchKernelGGL(validate_rows, dim3((unsigned)((I + 255) / 256)), dim3(256), 0, st, d->row_ptr, d->item_idx,
-                       d->c, d->a, I, J, m, nnz, dflags, d_amax, d_nonunit);
-    DL_HIP_TRY(hipGetLastError());
-  }
-  int hflags[16];
-  DL_HIP_TRY(hipMemcpyAsync(hflags, dflags, sizeof(hflags), hipMemcpyDeviceToHost, st));
-  DL_HIP_TRY(hipStreamSynchronize(st));
-  DL_CHECK_ARG(!(hflags[0] & F_RANGE), "item_idx out of range [0, n_items)");
-  DL_CHECK_ARG(!(hflags[0] & F_ORDER), "item_idx must be strictly increasing within each row");
-  DL_CHECK_ARG(!(hflags[0] & F_CNAN), "c has a non-finite entry");
-  DL_CHECK_ARG(!(hflags[0] & F_ANAN), "a has a non-finite entry");
-  float amax[DL_MAX_FAMILIES] = {1.f, 1.f, 1.f, 1.f};
-  int fam_of_slot[DL_MAX_FAMILIES] = {0, 0, 0, 0};
-  P->n_stored = 0;
-  for (int k = 0; k < m; ++k) {
-    if (d->a && hflags[8 + k]) {
-      P->a_slot[k] = P->n_stored;
-      fam_of_slot[P->n_stored++] = k;
-      float mx;
-      memcpy(&mx, &hflags[4 + k], 4);
-      amax[k] = mx;
-    } else {
-      P->a_slot[k] = -1;
-      amax[k] = 1.f;
-    }
-  }
-  P->has_a = P->n_stored > 0;
-
   // ---- library-owned layout ----
   const bool bf16 = P->storage == DL_BF16;
   const size_t vb = bf16 ? 2 : 4;
   DL_TRY(dmalloc(P, &P->rp, (size_t)I + 1));
-  DL_TRY(dmalloc(P, &P->idx, (size_t)nnz));
+  const int64_t stride = nnz + DL_PAD;
+  DL_TRY(dmalloc(P, &P->idx, (size_t)stride));
+  DL_HIP_TRY(hipMemsetAsync(P->idx + nnz, 0, sizeof(int32_t) * DL_PAD, st));
   {
     unsigned char* cv = nullptr;
-    DL_TRY(dmalloc(P, &cv, (size_t)nnz * vb));
+    DL_TRY(dmalloc(P, &cv, (size_t)stride * vb));
+    DL_HIP_TRY(hipMemsetAsync(cv + (size_t)nnz * vb, 0, (size_t)DL_PAD * vb, st));
     P->cval = cv;
   }
   if (P->n_stored > 0) {
     unsigned char* av = nullptr;
-    DL_TRY(dmalloc(P, &av, (size_t)nnz * vb * (size_t)P->n_stored));
+    DL_TRY(dmalloc(P, &av, (size_t)stride * vb * (size_t)P->n_stored));
+    DL_HIP_TRY(hipMemsetAsync(av, 0, (size_t)stride * vb * (size_t)P->n_stored, st));
     P->aval = av;
   }
   DL_TRY(dmalloc(P, &P->orig_rp, (size_t)std::max<int64_t>(I, 1)));
