@@ -44,6 +44,26 @@ def make_instance(args):
     return inst, desc
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("dl_grad.hip", "dl_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2606_07777_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(args):
+    """HBM bytes per gradient pass from the committed rocprofv3 counter summary, when it
+    was taken on the current kernel source and this workload; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "grad_pass_production_traffic.json")
+    if not os.path.exists(path) or args.workload != "production" or args.storage != "f32":
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha1") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_pass")
+
+
 def cpu_baseline(inst, budget_s: float):
     """The FP64 oracle on a bounded sample of the same instance: first S users."""
     import numpy as np
@@ -75,7 +95,10 @@ def main():
     ap.add_argument("--users", type=int, default=10_000_000)
     ap.add_argument("--items", type=int, default=10_000)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"])
-    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=8, help="largest workgroups-per-CU grid the tuner may pick")
+    ap.add_argument("--tune-rounds", type=int, default=3, help="workgroup-split balancing rounds (0 = off)")
+    ap.add_argument("--copy-ref-mb", type=int, default=0,
+                    help="run a device copy of this size first (reference kernel for counter scaling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--solve", action="store_true", help="also time a cold solve to a 1e-4 certified gap")
@@ -93,6 +116,14 @@ def main():
 
     inst, desc = make_instance(args)
     torch.cuda.set_device(0)
+    if args.copy_ref_mb:
+        n = args.copy_ref_mb * 1024 * 1024 // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"reference copy: {args.copy_ref_mb} MiB read, {args.copy_ref_mb} MiB written")
     t = time.time()
     prob = dl.Problem.from_instance(inst, storage=args.storage, jacobi=True, wg_per_cu=args.wg_per_cu)
     torch.cuda.synchronize()
@@ -106,6 +137,10 @@ def main():
     s.step(args.warmup)
     s.set_stage(1e-2, 1.0, True)
     s.step(5)
+    tune = None
+    if args.tune_rounds > 0:
+        tune = s.autotune(args.tune_rounds)
+        log(f"workgroup split tuned: {tune}")
     torch.cuda.synchronize()
     log("warm-up done")
 
@@ -143,9 +178,10 @@ def main():
         "config": {"workload": desc, "n_users": inst.n_users, "n_items": inst.n_items, "nnz": inst.nnz,
                    "storage": args.storage, "gamma_timed": 1e-2, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args),
                      "kernel": "grad_pass", "kernel_ms": grad_ms, "bytes_per_pass": bytes_pass},
         "update_ms": upd_ms,
+        "schedule": tune,
     }
     del s
     if args.solve:

@@ -64,6 +64,7 @@ typedef enum { DL_F32 = 0, DL_BF16 = 1 } dl_storage;
 
 typedef struct dl_problem dl_problem;
 typedef struct dl_solver dl_solver;
+typedef struct dl_batch dl_batch;
 
 typedef struct {
   int64_t n_users;          /* I >= 0 */
@@ -78,7 +79,7 @@ typedef struct {
   int32_t storage;          /* dl_storage */
   double radius;            /* z (simplex) or u (box), > 0 */
   int32_t jacobi;           /* 1: Jacobi row scaling in the solver (Appendix C) */
-  int32_t wg_per_cu;        /* gradient-pass workgroups per compute unit, 0 = default */
+  int32_t wg_per_cu;        /* gradient-pass workgroups per compute unit, 0 = default (4) */
   void* stream;             /* hipStream_t */
 } dl_problem_desc;
 
@@ -143,7 +144,7 @@ typedef struct {
   double tol;              /* stop when the certified relative gap <= tol (final stage) */
   int64_t max_iters;       /* total iteration cap */
   int32_t reset_momentum;  /* 1: restart the momentum at each stage switch */
-  int32_t pad0;
+  int32_t autotune_rounds; /* > 0: dl_solver_autotune once, after up to 50 iterations of stage 0 */
   double step_scale;       /* step = step_scale * gamma / lhat */
 } dl_solve_opts;
 
@@ -193,6 +194,54 @@ typedef struct {
 dl_status dl_solver_enable_timing(dl_solver* s, int32_t on);
 /* Synchronises and returns the sums since timing was enabled. */
 dl_status dl_solver_get_timing(dl_solver* s, dl_timing* out);
+
+/* ----------------------------------------------------------------------- */
+/* Many independent instances in one launch per iteration phase.           */
+/* ----------------------------------------------------------------------- */
+/*
+ * Groups n created problems (n >= 1; same device, stream, storage and kernel
+ * variant: the same family count class and whether a is stored).  The batch
+ * borrows the problems: they must outlive it and must not be used by other
+ * calls while a batch solve runs.  DL_EUNSUPPORTED for mixed variants.
+ */
+dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_batch** out);
+void dl_batch_destroy(dl_batch* batch); /* NULL-safe; does not destroy the problems */
+/*
+ * Solves every member with the same schedule as dl_solve, in lockstep: each
+ * iteration is one gradient-pass launch over all live members (workgroups
+ * dealt by pass cost) plus one update launch.  Members leave the launch when
+ * their certified gap reaches tol at a check point of the final stage.
+ *   lambda0     host array of n device pointers (m_i*J_i each), or NULL (zeros)
+ *   lambda_out  host array of n device pointers (m_i*J_i each)
+ *   stats       host array of n records (iters and status per member)
+ * Returns DL_OK when every member converged, DL_NOT_CONVERGED when some hit
+ * the cap (results valid), or an error.
+ */
+dl_status dl_batch_solve(dl_batch* batch, const dl_solve_opts* opts, const double* const* lambda0,
+                         double* const* lambda_out, dl_solve_stats* stats);
+
+/* ----------------------------------------------------------------------- */
+/* Workgroup schedule tuning                                               */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_workgroups;     /* gradient-pass grid kept */
+  int32_t rounds;           /* balancing rounds per candidate grid */
+  double pass_ms_model;     /* mean pass time, cost-model split, at the kept grid */
+  double pass_ms_tuned;     /* mean pass time after balancing */
+  double imbalance_model;   /* max / mean workgroup time before balancing */
+  double imbalance_tuned;   /* the same after */
+} dl_tune_result;
+
+/*
+ * Tunes the gradient pass's workgroup schedule at the solver's current point
+ * (call it after some iterations, so the active sets are realistic): for
+ * grids of 1, 2, 4, ... workgroups per compute unit (up to what the problem
+ * was created with), the task split is re-balanced `rounds` times from
+ * measured per-workgroup times (steady-clock stamps), and the fastest grid and
+ * split are kept for every later pass of this problem.  Does not change the
+ * solver's iterate.  Synchronises the stream.
+ */
+dl_status dl_solver_autotune(dl_solver* s, int32_t rounds, dl_tune_result* out);
 
 /* Message for the last non-OK status on this thread. */
 const char* dl_last_error(void);

@@ -80,7 +80,7 @@ class dl_solve_opts(ctypes.Structure):
         ("tol", ctypes.c_double),
         ("max_iters", ctypes.c_int64),
         ("reset_momentum", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("autotune_rounds", ctypes.c_int32),
         ("step_scale", ctypes.c_double),
     ]
 
@@ -102,6 +102,17 @@ class dl_solve_stats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class dl_tune_result(ctypes.Structure):
+    _fields_ = [
+        ("n_workgroups", ctypes.c_int32),
+        ("rounds", ctypes.c_int32),
+        ("pass_ms_model", ctypes.c_double),
+        ("pass_ms_tuned", ctypes.c_double),
+        ("imbalance_model", ctypes.c_double),
+        ("imbalance_tuned", ctypes.c_double),
+    ]
 
 
 class dl_timing(ctypes.Structure):
@@ -130,6 +141,11 @@ SIGNATURES = {
     "dl_solver_certificate": ([_VP, ctypes.POINTER(dl_solve_stats)], _I32),
     "dl_solver_enable_timing": ([_VP, _I32], _I32),
     "dl_solver_get_timing": ([_VP, ctypes.POINTER(dl_timing)], _I32),
+    "dl_solver_autotune": ([_VP, _I32, ctypes.POINTER(dl_tune_result)], _I32),
+    "dl_batch_create": ([_I32, ctypes.POINTER(_VP), ctypes.POINTER(_VP)], _I32),
+    "dl_batch_destroy": ([_VP], None),
+    "dl_batch_solve": ([_VP, ctypes.POINTER(dl_solve_opts), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                        ctypes.POINTER(dl_solve_stats)], _I32),
     "dl_last_error": ([], ctypes.c_char_p),
 }
 
@@ -255,13 +271,13 @@ class Problem:
         return x
 
     def solve(self, gammas: Sequence[float], iters: Sequence[int], tol=1e-4, max_iters=20000, check_every=10,
-              reset_momentum=True, step_scale=1.0, lam0=None):
+              reset_momentum=True, step_scale=1.0, lam0=None, autotune_rounds=0):
         """dl_solve over the schedule; returns (lam tensor f64 [m*J], stats dict)."""
         torch = self.torch
         g = np.ascontiguousarray(gammas, dtype=np.float64)
         it = np.ascontiguousarray(iters, dtype=np.int64)
         o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
-                          int(reset_momentum), 0, float(step_scale))
+                          int(reset_momentum), int(autotune_rounds), float(step_scale))
         l0 = None if lam0 is None else lam0.to(device="cuda", dtype=torch.float64).contiguous()
         out = self._empty(self.m * self.J, torch.float64)
         st = dl_solve_stats()
@@ -311,6 +327,12 @@ class Solver:
         _check(load().dl_solver_certificate(self.handle, ctypes.byref(st)))
         return st.as_dict()
 
+    def autotune(self, rounds: int = 3) -> dict:
+        """dl_solver_autotune: balance the workgroup split from measured times."""
+        r = dl_tune_result()
+        _check(load().dl_solver_autotune(self.handle, int(rounds), ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in r._fields_}
+
     def enable_timing(self, on: bool = True):
         _check(load().dl_solver_enable_timing(self.handle, int(on)))
 
@@ -318,3 +340,45 @@ class Solver:
         t = dl_timing()
         _check(load().dl_solver_get_timing(self.handle, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in t._fields_}
+
+
+class Batch:
+    """dl_batch_*: several problems solved in lockstep, one launch per iteration phase."""
+
+    def __init__(self, probs):
+        self.probs = list(probs)
+        arr = (ctypes.c_void_p * len(self.probs))(*[p.handle.value for p in self.probs])
+        h = ctypes.c_void_p()
+        _check(load().dl_batch_create(len(self.probs), arr, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, gammas, iters, tol=1e-4, max_iters=20000, check_every=10, reset_momentum=True,
+              step_scale=1.0, lam0=None):
+        """Returns ([lam tensor per member], [stats dict per member])."""
+        torch = self.probs[0].torch
+        n = len(self.probs)
+        g = np.ascontiguousarray(gammas, dtype=np.float64)
+        it = np.ascontiguousarray(iters, dtype=np.int64)
+        o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
+                          int(reset_momentum), 0, float(step_scale))
+        outs = [p._empty(p.m * p.J, torch.float64) for p in self.probs]
+        out_arr = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
+        l0 = None
+        if lam0 is not None:
+            l0t = [t.to(device="cuda", dtype=torch.float64).contiguous() for t in lam0]
+            l0 = (ctypes.c_void_p * n)(*[_ptr(t) for t in l0t])
+        stats = (dl_solve_stats * n)()
+        _check(load().dl_batch_solve(self.handle, ctypes.byref(o), l0, out_arr, stats),
+               allow=(DL_OK, DL_NOT_CONVERGED))
+        return outs, [s.as_dict() for s in stats]

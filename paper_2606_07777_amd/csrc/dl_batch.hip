@@ -1,0 +1,363 @@
+// Many independent instances solved together: one gradient-pass launch and one
+// update launch per iteration serve every live instance, whatever its size.
+//
+// Workgroups are dealt to instances in proportion to their pass cost (several
+// per compute unit, so the hardware's workgroup dispatch evens out what the
+// static split leaves uneven).  Each workgroup serves a contiguous task range
+// of one instance and writes its integer histogram into that instance's own
+// partial slots, so every instance's gradient is bitwise the one its solo pass
+// gives.  All instances follow the same gamma schedule in lockstep; the
+// certificate runs per instance at the check points of the final stage, and
+// converged instances leave the launch tables.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <numeric>
+
+#include "dl_common.h"
+
+struct dl_solver;  // dl_solver.hip
+dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag);
+
+namespace {
+
+struct bupd {
+  const unsigned long long* part;
+  int n_slot;
+  int mJ, J;
+  int pad;
+  double inv_q[DL_MAX_FAMILIES];
+  const double* D;
+  const double* b;
+  double* lam;
+  double* y;
+  float* mu_y;
+  float* mu_lam;
+  int* flag;
+  double lhat;
+};
+
+struct bblk {
+  int inst;
+  int r0;
+};
+
+// The fused accelerated step of every live instance (same arithmetic as the
+// single-instance update): reduce the partial slots in fixed order, step on the
+// Jacobi-scaled dual, FISTA momentum, next gather point.
+__global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict__ blk, double gamma,
+                             double step_scale, double beta) {
+  const bblk B = blk[blockIdx.x];
+  const bupd& u = U[B.inst];
+  const int r = B.r0 + (int)threadIdx.x;
+  if (r >= u.mJ) return;
+  long long acc = 0;
+  for (int w = 0; w < u.n_slot; ++w) acc += (long long)u.part[(size_t)w * u.mJ + r];
+  const double ax = (double)acc * u.inv_q[r / u.J];
+  const double Dr = u.D[r];
+  const double eta = step_scale * gamma / u.lhat;
+  const double gs = Dr * (ax - u.b[r]);
+  const double lo = u.lam[r];
+  const double ln = fmax(0.0, u.y[r] + eta * gs);
+  const double yn = ln + beta * (ln - lo);
+  u.lam[r] = ln;
+  u.y[r] = yn;
+  u.mu_y[r] = (float)(Dr * yn);
+  u.mu_lam[r] = (float)(Dr * ln);
+  if (!isfinite(ln) || !isfinite(yn)) atomicOr(u.flag, 1);
+}
+
+}  // namespace
+
+struct dl_batch {
+  int n = 0;
+  std::vector<dl_problem*> probs;
+  std::vector<dl_solver*> solvers;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  int wg_per_cu = 4;
+  // device tables
+  dl_grad_args* d_args = nullptr;
+  dl_wg_desc* d_wgs = nullptr;
+  bupd* d_upd = nullptr;
+  bblk* d_blk = nullptr;
+  unsigned long long* d_part = nullptr;
+  size_t part_cap = 0;
+  int n_wg = 0, n_blk = 0;
+  size_t lds = 0;
+  // host mirrors
+  std::vector<dl_grad_args> h_args;
+  std::vector<dl_wg_desc> h_wgs;
+  std::vector<bupd> h_upd;
+  std::vector<bblk> h_blk;
+};
+
+static void free_batch(dl_batch* B) {
+  if (!B) return;
+  for (dl_solver* s : B->solvers) dl_solver_destroy(s);
+  void* ptrs[] = {B->d_args, B->d_wgs, B->d_upd, B->d_blk, B->d_part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete B;
+}
+
+// Rebuilds the launch tables for the live instances at gamma.
+static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double gamma) {
+  // earlier launches may still read the tables about to be replaced
+  DL_HIP_TRY(hipStreamSynchronize(B->stream));
+  std::vector<double> cost(live.size());
+  double tot = 0.0;
+  for (size_t q = 0; q < live.size(); ++q) {
+    const dl_problem* P = B->probs[live[q]];
+    cost[q] = (double)P->nnz + 64.0 * (double)P->n_tasks;
+    tot += cost[q];
+  }
+  const int budget = std::max<int>((int)live.size(), B->n_cu * B->wg_per_cu);
+  // workgroups per instance: largest-remainder rounding of the cost share, >= 1 with tasks
+  std::vector<int> w(live.size(), 0);
+  std::vector<std::pair<double, int>> rem;
+  int used = 0;
+  for (size_t q = 0; q < live.size(); ++q) {
+    const dl_problem* P = B->probs[live[q]];
+    if (P->n_tasks == 0) continue;
+    double share = tot > 0 ? cost[q] / tot * budget : 1.0;
+    w[q] = std::max(1, (int)floor(share));
+    w[q] = (int)std::min<int64_t>(w[q], P->n_tasks);
+    used += w[q];
+    rem.push_back({share - floor(share), (int)q});
+  }
+  std::sort(rem.begin(), rem.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  for (auto& r : rem) {
+    if (used >= budget) break;
+    const dl_problem* P = B->probs[live[r.second]];
+    if (w[r.second] < P->n_tasks) {
+      ++w[r.second];
+      ++used;
+    }
+  }
+  B->h_wgs.clear();
+  B->h_upd.clear();
+  B->h_blk.clear();
+  size_t part_need = 0, lds = 0;
+  std::vector<size_t> part_off(live.size(), 0);
+  for (size_t q = 0; q < live.size(); ++q) {
+    const dl_problem* P = B->probs[live[q]];
+    part_off[q] = part_need;
+    part_need += (size_t)std::max(1, w[q]) * (size_t)P->m * P->J;
+    lds = std::max(lds, dl_grad_lds_bytes(P, M_HIST));
+  }
+  if (part_need > B->part_cap) {
+    if (B->d_part) DL_HIP_TRY(hipFree(B->d_part));
+    B->d_part = nullptr;
+    DL_HIP_TRY(hipMalloc((void**)&B->d_part, part_need * sizeof(unsigned long long)));
+    B->part_cap = part_need;
+  }
+  B->h_args.assign(B->n, dl_grad_args());
+  for (size_t q = 0; q < live.size(); ++q) {
+    const int i = live[q];
+    const dl_problem* P = B->probs[i];
+    double *lam, *y;
+    float *mu_y, *mu_lam;
+    int* flag;
+    DL_TRY(dl_solver_state(B->solvers[i], &lam, &y, &mu_y, &mu_lam, &flag));
+    dl_grad_args A = dl_make_grad_args(P, mu_y, gamma);
+    A.part = B->d_part + part_off[q];
+    B->h_args[i] = A;
+    // contiguous task ranges of this instance, balanced by slot count
+    const int64_t T = P->n_tasks;
+    for (int k = 0; k < w[q]; ++k) {
+      dl_wg_desc d;
+      d.inst = i;
+      d.slot = k;
+      d.t0 = T * k / w[q];
+      d.t1 = T * (k + 1) / w[q];
+      B->h_wgs.push_back(d);
+    }
+    bupd u;
+    memset(&u, 0, sizeof(u));
+    u.part = A.part;
+    u.n_slot = w[q];
+    u.mJ = P->m * P->J;
+    u.J = P->J;
+    for (int k = 0; k < DL_MAX_FAMILIES; ++k) u.inv_q[k] = P->qscale[k] > 0.f ? 1.0 / (double)P->qscale[k] : 0.0;
+    u.D = P->D;
+    u.b = P->b;
+    u.lam = lam;
+    u.y = y;
+    u.mu_y = mu_y;
+    u.mu_lam = mu_lam;
+    u.flag = flag;
+    u.lhat = P->lhat;
+    const int ui = (int)B->h_upd.size();
+    B->h_upd.push_back(u);
+    for (int r0 = 0; r0 < u.mJ; r0 += 256) B->h_blk.push_back({ui, r0});
+  }
+  B->n_wg = (int)B->h_wgs.size();
+  B->n_blk = (int)B->h_blk.size();
+  B->lds = lds;
+  if (B->d_wgs) DL_HIP_TRY(hipFree(B->d_wgs));
+  if (B->d_upd) DL_HIP_TRY(hipFree(B->d_upd));
+  if (B->d_blk) DL_HIP_TRY(hipFree(B->d_blk));
+  B->d_wgs = nullptr;
+  B->d_upd = nullptr;
+  B->d_blk = nullptr;
+  DL_HIP_TRY(hipMalloc((void**)&B->d_wgs, sizeof(dl_wg_desc) * std::max<size_t>(1, B->h_wgs.size())));
+  DL_HIP_TRY(hipMalloc((void**)&B->d_upd, sizeof(bupd) * std::max<size_t>(1, B->h_upd.size())));
+  DL_HIP_TRY(hipMalloc((void**)&B->d_blk, sizeof(bblk) * std::max<size_t>(1, B->h_blk.size())));
+  hipStream_t st = B->stream;
+  DL_HIP_TRY(hipMemcpyAsync(B->d_args, B->h_args.data(), sizeof(dl_grad_args) * B->n, hipMemcpyHostToDevice, st));
+  if (!B->h_wgs.empty())
+    DL_HIP_TRY(hipMemcpyAsync(B->d_wgs, B->h_wgs.data(), sizeof(dl_wg_desc) * B->h_wgs.size(), hipMemcpyHostToDevice,
+                              st));
+  if (!B->h_upd.empty())
+    DL_HIP_TRY(hipMemcpyAsync(B->d_upd, B->h_upd.data(), sizeof(bupd) * B->h_upd.size(), hipMemcpyHostToDevice, st));
+  if (!B->h_blk.empty())
+    DL_HIP_TRY(hipMemcpyAsync(B->d_blk, B->h_blk.data(), sizeof(bblk) * B->h_blk.size(), hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipStreamSynchronize(st));  // host tables must outlive the copies
+  return DL_OK;
+}
+
+extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_batch** out) {
+  DL_CHECK_ARG(out, "out is NULL");
+  *out = nullptr;
+  DL_CHECK_ARG(n >= 1 && probs, "need at least one problem");
+  for (int i = 0; i < n; ++i) DL_CHECK_ARG(probs[i], "NULL problem in batch");
+  const dl_problem* P0 = probs[0];
+  for (int i = 1; i < n; ++i) {
+    const dl_problem* P = probs[i];
+    if (P->device != P0->device || P->stream != P0->stream || P->mf != P0->mf || P->has_a != P0->has_a ||
+        P->storage != P0->storage || P->kmax != P0->kmax) {
+      dl_set_error("batch members must share device, stream, storage and kernel variant (families, stored a)");
+      return DL_EUNSUPPORTED;
+    }
+  }
+  dl_batch* B = new (std::nothrow) dl_batch();
+  if (!B) {
+    dl_set_error("host allocation failed");
+    return DL_ENOMEM;
+  }
+  B->n = n;
+  B->probs.assign(probs, probs + n);
+  B->stream = P0->stream;
+  auto fail = [&](dl_status s) {
+    free_batch(B);
+    return s;
+  };
+  if (hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, P0->device) != hipSuccess) {
+    dl_set_error("hipDeviceGetAttribute failed");
+    return fail(DL_EHIP);
+  }
+  if (hipMalloc((void**)&B->d_args, sizeof(dl_grad_args) * n) != hipSuccess) {
+    dl_set_error("device allocation failed");
+    return fail(DL_ENOMEM);
+  }
+  *out = B;
+  return DL_OK;
+}
+
+extern "C" void dl_batch_destroy(dl_batch* B) { free_batch(B); }
+
+extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const double* const* lambda0,
+                                    double* const* lambda_out, dl_solve_stats* stats) {
+  DL_CHECK_ARG(B && o && lambda_out && stats, "NULL argument");
+  DL_CHECK_ARG(o->n_stages >= 1 && o->gammas && o->iters, "empty schedule");
+  for (int s = 0; s < o->n_stages; ++s) {
+    DL_CHECK_ARG(o->gammas[s] > 0.0 && isfinite(o->gammas[s]), "gamma must be positive and finite");
+    DL_CHECK_ARG(o->iters[s] >= 0 || s == o->n_stages - 1, "only the last stage may run until tol");
+  }
+  for (int i = 0; i < B->n; ++i) DL_CHECK_ARG(lambda_out[i], "NULL lambda_out entry");
+  const double step_scale = o->step_scale > 0.0 ? o->step_scale : 1.0;
+  auto t0 = std::chrono::steady_clock::now();
+  for (dl_solver* s : B->solvers) dl_solver_destroy(s);
+  B->solvers.assign(B->n, nullptr);
+  for (int i = 0; i < B->n; ++i) {
+    memset(&stats[i], 0, sizeof(stats[i]));
+    DL_TRY(dl_solver_create(B->probs[i], lambda0 ? lambda0[i] : nullptr, &B->solvers[i]));
+  }
+  std::vector<int> live(B->n);
+  std::iota(live.begin(), live.end(), 0);
+  std::vector<char> done(B->n, 0);
+  std::vector<int64_t> iters(B->n, 0), checks(B->n, 0);
+  std::vector<int> last_stage(B->n, 0);
+  dl_status rc = DL_OK;
+  int64_t total = 0;
+  for (int stage = 0; stage < o->n_stages && rc == DL_OK && !live.empty(); ++stage) {
+    const double gamma = o->gammas[stage];
+    for (int i : live) {
+      rc = dl_solver_set_stage(B->solvers[i], gamma, step_scale, stage == 0 ? 1 : o->reset_momentum);
+      if (rc != DL_OK) break;
+      last_stage[i] = stage;
+    }
+    if (rc != DL_OK) break;
+    DL_TRY(build_tables(B, live, gamma));
+    const bool last = stage == o->n_stages - 1;
+    const int64_t n_it = o->iters[stage];
+    double tk = 1.0;
+    int64_t k = 0;
+    while ((n_it < 0 || k < n_it) && total < o->max_iters && !live.empty()) {
+      rc = dl_launch_grad_batch(B->probs[live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream);
+      if (rc != DL_OK) break;
+      const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
+      const double beta = (tk - 1.0) / tn;
+      tk = tn;
+      hipLaunchKernelGGL(update_batch, dim3(B->n_blk), dim3(256), 0, B->stream, B->d_upd, B->d_blk, gamma,
+                         step_scale, beta);
+      if (hipGetLastError() != hipSuccess) {
+        dl_set_error("update_batch launch failed");
+        rc = DL_EHIP;
+        break;
+      }
+      ++k;
+      ++total;
+      for (int i : live) ++iters[i];
+      if (last && o->check_every > 0 && k % o->check_every == 0) {
+        std::vector<int> keep;
+        for (int i : live) {
+          dl_status cs = dl_solver_certificate(B->solvers[i], &stats[i]);
+          ++checks[i];
+          if (cs != DL_OK) {
+            stats[i].status = cs;
+            done[i] = 1;
+            continue;
+          }
+          if (stats[i].rel_gap <= o->tol) {
+            stats[i].status = DL_OK;
+            done[i] = 1;
+          } else {
+            keep.push_back(i);
+          }
+        }
+        if (keep.size() != live.size()) {
+          live = keep;
+          if (!live.empty()) DL_TRY(build_tables(B, live, gamma));
+        }
+      }
+      if (n_it < 0 && o->check_every == 0 && total >= o->max_iters) break;
+    }
+  }
+  for (int i = 0; i < B->n && rc == DL_OK; ++i) {
+    if (!done[i]) {
+      dl_status cs = dl_solver_certificate(B->solvers[i], &stats[i]);
+      ++checks[i];
+      stats[i].status = (cs == DL_OK) ? (stats[i].rel_gap <= o->tol ? DL_OK : DL_NOT_CONVERGED) : cs;
+    }
+    dl_status ls = dl_solver_get_lambda(B->solvers[i], lambda_out[i]);
+    if (ls != DL_OK) rc = ls;
+  }
+  if (rc == DL_OK) DL_HIP_TRY(hipStreamSynchronize(B->stream));
+  const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  bool all_ok = true;
+  for (int i = 0; i < B->n; ++i) {
+    stats[i].iters = iters[i];
+    stats[i].stage = last_stage[i];
+    stats[i].n_checks = checks[i];
+    stats[i].wall_ms = wall;
+    if (stats[i].status != DL_OK) all_ok = false;
+  }
+  for (dl_solver* s : B->solvers) dl_solver_destroy(s);
+  B->solvers.clear();
+  if (rc != DL_OK) return rc;
+  return all_ok ? DL_OK : DL_NOT_CONVERGED;
+}

@@ -105,6 +105,15 @@ struct dl_grad_args {
   unsigned long long* part;         // n_wg * m*J
   double* obj_part;                 // n_wg
   float* x_out;                     // nnz caller order, nullable
+  unsigned long long* wg_clock;     // nullable: per slot (start, end) steady-clock ticks
+};
+
+// Workgroup descriptor of a batched pass: tasks [t0, t1) of instance inst,
+// histogram into that instance's partial slot.
+struct dl_wg_desc {
+  int32_t inst;
+  int32_t slot;
+  int64_t t0, t1;
 };
 
 struct dl_problem {
@@ -131,8 +140,13 @@ struct dl_problem {
   // task table
   std::vector<dl_bucket> buckets;
   int64_t n_tasks = 0;
-  int n_wg = 0;
-  int64_t* wg_task = nullptr;
+  int n_wg = 0;          // workgroups of the current partition
+  int n_wg_cap = 0;      // partial-sum slots allocated
+  int n_cu = 0;
+  int64_t* wg_task = nullptr;              // n_wg_cap + 1
+  std::vector<float> task_cost;            // cost-model weight of every task
+  unsigned long long* wg_clock = nullptr;  // 2 * n_wg_cap
+  bool clocking = false;
 
   // item space (device)
   double* b = nullptr;       // m*J
@@ -142,6 +156,7 @@ struct dl_problem {
 
   // per-pass scratch (device)
   unsigned long long* part = nullptr;  // n_wg * m*J
+  unsigned long long* acc = nullptr;   // m*J reduced sums, zero between passes
   double* obj_part = nullptr;          // n_wg
   double* pobj_part = nullptr;         // n_wg
   float* mu = nullptr;                 // m*J
@@ -156,6 +171,12 @@ struct dl_problem {
 dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double gamma,
                          const float* rfac, const float* v_in, float* x_out, double* obj_part);
 size_t dl_grad_lds_bytes(const dl_problem* P, int mode);
+dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamma);
+// Task ranges of n_wg workgroups with equal cost-model weight.
+std::vector<int64_t> dl_model_partition(const dl_problem* P, int n_wg);
+dl_status dl_set_partition(dl_problem* P, const std::vector<int64_t>& bounds);
+dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
+                               size_t lds, hipStream_t st);
 dl_status dl_grad_prepare(const dl_problem* P);
 
 // BF16 helpers (storage form: c and a in bfloat16, FP32 arithmetic).

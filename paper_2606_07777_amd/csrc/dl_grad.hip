@@ -478,8 +478,10 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
   if (MODE & (M_OBJ | M_REPAIR)) acc += (double)lobj;
 }
 
+// One workgroup's share of a pass: tasks [w0, w1) of the instance A describes;
+// its histogram goes to partial slot `slot`.
 template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__global__ void __launch_bounds__(DL_WG) grad_pass(dl_grad_args A) {
+__device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int64_t w1, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int mJ = A.m * A.J;
   const bool need_mu = !(MODE & M_VIN);
@@ -493,6 +495,8 @@ __global__ void __launch_bounds__(DL_WG) grad_pass(dl_grad_args A) {
   double* s_obj = reinterpret_cast<double*>(smem + off + (size_t)hist_n * 8);
 
   const int tid = threadIdx.x;
+  unsigned long long t_start = 0;
+  if (A.wg_clock && tid == 0) t_start = (unsigned long long)wall_clock64();
   for (int r = tid; r < mu_n; r += DL_WG) s_mu[r] = A.mu[r];
   for (int r = tid; r < rf_n; r += DL_WG) s_rf[r] = A.rfac[r];
   for (int r = tid; r < hist_n; r += DL_WG) s_hist[r] = 0ull;
@@ -500,8 +504,6 @@ __global__ void __launch_bounds__(DL_WG) grad_pass(dl_grad_args A) {
 
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  const int64_t w0 = A.wg_task[blockIdx.x];
-  const int64_t w1 = A.wg_task[blockIdx.x + 1];
   double acc = 0.0;
   for (int b = 0; b < A.n_buckets; ++b) {
     const dl_bucket& B = A.bk[b];
@@ -533,14 +535,35 @@ __global__ void __launch_bounds__(DL_WG) grad_pass(dl_grad_args A) {
   }
   __syncthreads();
   if (MODE & M_HIST) {
-    unsigned long long* dst = A.part + (size_t)blockIdx.x * mJ;
+    unsigned long long* dst = A.part + (size_t)slot * mJ;
     for (int r = tid; r < mJ; r += DL_WG) dst[r] = s_hist[r];
   }
   if ((MODE & (M_OBJ | M_REPAIR)) && tid == 0) {
     double tot = 0.0;
     for (int w = 0; w < DL_WAVES; ++w) tot += s_obj[w];
-    A.obj_part[blockIdx.x] = tot;
+    A.obj_part[slot] = tot;
   }
+  if (A.wg_clock) {
+    __syncthreads();
+    if (tid == 0) {
+      A.wg_clock[2 * slot] = t_start;
+      A.wg_clock[2 * slot + 1] = (unsigned long long)wall_clock64();
+    }
+  }
+}
+
+template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
+__global__ void __launch_bounds__(DL_WG) grad_pass(dl_grad_args A) {
+  grad_body<MF, HAS_A, KMAX, TV, MODE>(A, A.wg_task[blockIdx.x], A.wg_task[blockIdx.x + 1], (int)blockIdx.x);
+}
+
+// Many instances in one launch: workgroup w serves tasks [t0, t1) of
+// instance wgs[w].inst (per-instance arguments in device memory).
+template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
+__global__ void __launch_bounds__(DL_WG) grad_pass_batch(const dl_grad_args* __restrict__ args,
+                                                         const dl_wg_desc* __restrict__ wgs) {
+  const dl_wg_desc w = wgs[blockIdx.x];
+  grad_body<MF, HAS_A, KMAX, TV, MODE>(args[w.inst], w.t0, w.t1, w.slot);
 }
 
 template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
@@ -570,7 +593,18 @@ dl_status launch_storage(const dl_problem* P, int mode, const dl_grad_args& A, s
 }
 
 template <int MF, bool HAS_A, int KMAX, typename TV>
+dl_status launch_batch_t(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
+                         size_t lds, hipStream_t st) {
+  (void)P;
+  hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST>), dim3(n_wg), dim3(DL_WG), lds, st, d_args, d_wgs);
+  DL_HIP_TRY(hipGetLastError());
+  return DL_OK;
+}
+
+template <int MF, bool HAS_A, int KMAX, typename TV>
 void set_attr_all() {
+  (void)hipFuncSetAttribute((const void*)grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   const int big = 160 * 1024;
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
@@ -609,10 +643,21 @@ dl_status dl_grad_prepare(const dl_problem* P) {
   return DL_OK;
 }
 
-dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double gamma, const float* rfac,
-                         const float* v_in, float* x_out, double* obj_part) {
-  if (P->n_wg <= 0) return DL_OK;
-  if (x_out) mode |= M_XOUT;
+dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
+                               size_t lds, hipStream_t st) {
+  if (n_wg <= 0) return DL_OK;
+  const bool bf = P->storage == DL_BF16;
+  if (P->mf == 1 && !P->has_a)
+    return bf ? launch_batch_t<1, false, DL_KMAX_PLAIN, uint16_t>(P, n_wg, d_args, d_wgs, lds, st)
+              : launch_batch_t<1, false, DL_KMAX_PLAIN, float>(P, n_wg, d_args, d_wgs, lds, st);
+  if (P->mf == 1)
+    return bf ? launch_batch_t<1, true, DL_KMAX_A, uint16_t>(P, n_wg, d_args, d_wgs, lds, st)
+              : launch_batch_t<1, true, DL_KMAX_A, float>(P, n_wg, d_args, d_wgs, lds, st);
+  return bf ? launch_batch_t<4, true, DL_KMAX_A, uint16_t>(P, n_wg, d_args, d_wgs, lds, st)
+            : launch_batch_t<4, true, DL_KMAX_A, float>(P, n_wg, d_args, d_wgs, lds, st);
+}
+
+dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamma) {
   dl_grad_args A;
   memset(&A, 0, sizeof(A));
   A.rp = P->rp;
@@ -636,9 +681,18 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
   A.neg_inv_gamma = (float)(-1.0 / gamma);
   A.gamma = (float)gamma;
   A.mu = mu;
+  A.part = P->part;
+  A.wg_clock = P->clocking ? P->wg_clock : nullptr;
+  return A;
+}
+
+dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double gamma, const float* rfac,
+                         const float* v_in, float* x_out, double* obj_part) {
+  if (P->n_wg <= 0) return DL_OK;
+  if (x_out) mode |= M_XOUT;
+  dl_grad_args A = dl_make_grad_args(P, mu, gamma);
   A.rfac = rfac;
   A.v_in = v_in;
-  A.part = P->part;
   A.obj_part = obj_part;
   A.x_out = x_out;
   const size_t lds = dl_grad_lds_bytes(P, mode);

@@ -118,7 +118,7 @@ dl_status dmalloc(dl_problem* P, T** p, size_t n) {
 
 void free_problem(dl_problem* P) {
   if (!P) return;
-  void* ptrs[] = {P->rp, P->idx, P->cval, P->aval, P->orig_rp, P->wg_task, P->b, P->D, P->part,
+  void* ptrs[] = {P->rp, P->idx, P->cval, P->aval, P->orig_rp, P->wg_task, P->wg_clock, P->b, P->D, P->part, P->acc,
                   P->obj_part, P->pobj_part, P->mu, P->rfac, P->lam_tmp, P->cert_out};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -263,24 +263,13 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
 
   int n_cu = 0;
   DL_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
-  const int wpc = d->wg_per_cu > 0 ? d->wg_per_cu : 1;
+  P->n_cu = n_cu;
+  const int wpc = d->wg_per_cu > 0 ? d->wg_per_cu : 4;
   int64_t n_wg = std::min<int64_t>((int64_t)n_cu * wpc, (P->n_tasks + DL_WAVES - 1) / DL_WAVES);
   if (P->n_tasks > 0 && n_wg < 1) n_wg = 1;
-  P->n_wg = (int)n_wg;
-  std::vector<int64_t> wg_task((size_t)n_wg + 1, 0);
-  {
-    double tot = 0.0;
-    for (double c : task_cost) tot += c;
-    double run = 0.0;
-    int64_t t = 0;
-    for (int64_t w = 1; w < n_wg; ++w) {
-      double target = tot * (double)w / (double)n_wg;
-      while (t < P->n_tasks && run + task_cost[(size_t)t] * 0.5 < target) run += task_cost[(size_t)t++];
-      wg_task[(size_t)w] = t;
-    }
-    wg_task[(size_t)n_wg] = P->n_tasks;
-  }
-
+  P->task_cost.assign(task_cost.begin(), task_cost.end());
+  P->n_wg_cap = (int)std::max<int64_t>(n_wg, 1);
+  std::vector<int64_t> wg_task = dl_model_partition(P, (int)n_wg);
   // ---- library-owned layout ----
   const bool bf16 = P->storage == DL_BF16;
   const size_t vb = bf16 ? 2 : 4;
@@ -301,12 +290,12 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
     P->aval = av;
   }
   DL_TRY(dmalloc(P, &P->orig_rp, (size_t)std::max<int64_t>(I, 1)));
-  DL_TRY(dmalloc(P, &P->wg_task, (size_t)n_wg + 1));
+  DL_TRY(dmalloc(P, &P->wg_task, (size_t)P->n_wg_cap + 1));
+  DL_TRY(dmalloc(P, &P->wg_clock, 2 * (size_t)P->n_wg_cap));
   DL_HIP_TRY(hipMemcpyAsync(P->rp, new_rp.data(), sizeof(int64_t) * (size_t)(I + 1), hipMemcpyHostToDevice, st));
   if (I > 0)
     DL_HIP_TRY(hipMemcpyAsync(P->orig_rp, orig_rp.data(), sizeof(int64_t) * (size_t)I, hipMemcpyHostToDevice, st));
-  DL_HIP_TRY(hipMemcpyAsync(P->wg_task, wg_task.data(), sizeof(int64_t) * (size_t)(n_wg + 1), hipMemcpyHostToDevice,
-                            st));
+  DL_TRY(dl_set_partition(P, wg_task));
   int* d_slot = dflags + 12;  // fam_of_slot (n_stored <= 4)
   DL_HIP_TRY(hipMemcpyAsync(d_slot, fam_of_slot, sizeof(int) * 4, hipMemcpyHostToDevice, st));
   if (I > 0) {
@@ -393,9 +382,11 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   DL_TRY(dmalloc(P, &P->D, (size_t)mJ));
   DL_HIP_TRY(hipMemcpyAsync(P->b, P->b_host.data(), sizeof(double) * (size_t)mJ, hipMemcpyHostToDevice, st));
   DL_HIP_TRY(hipMemcpyAsync(P->D, P->D_host.data(), sizeof(double) * (size_t)mJ, hipMemcpyHostToDevice, st));
-  DL_TRY(dmalloc(P, &P->part, (size_t)std::max(1, P->n_wg) * (size_t)mJ));
-  DL_TRY(dmalloc(P, &P->obj_part, (size_t)std::max(1, P->n_wg)));
-  DL_TRY(dmalloc(P, &P->pobj_part, (size_t)std::max(1, P->n_wg)));
+  DL_TRY(dmalloc(P, &P->part, (size_t)P->n_wg_cap * (size_t)mJ));
+  DL_TRY(dmalloc(P, &P->acc, (size_t)mJ));
+  DL_HIP_TRY(hipMemsetAsync(P->acc, 0, sizeof(unsigned long long) * (size_t)mJ, st));
+  DL_TRY(dmalloc(P, &P->obj_part, (size_t)P->n_wg_cap));
+  DL_TRY(dmalloc(P, &P->pobj_part, (size_t)P->n_wg_cap));
   DL_TRY(dmalloc(P, &P->mu, (size_t)mJ));
   DL_TRY(dmalloc(P, &P->rfac, (size_t)J));
   DL_TRY(dmalloc(P, &P->lam_tmp, (size_t)mJ));
@@ -407,6 +398,40 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
 }
 
 }  // namespace
+
+std::vector<int64_t> dl_model_partition(const dl_problem* P, int n_wg) {
+  std::vector<int64_t> bounds((size_t)std::max(n_wg, 0) + 1, 0);
+  if (n_wg <= 0) return bounds;
+  double tot = 0.0;
+  for (float c : P->task_cost) tot += c;
+  double run = 0.0;
+  int64_t t = 0;
+  for (int w = 1; w < n_wg; ++w) {
+    const double target = tot * (double)w / (double)n_wg;
+    while (t < P->n_tasks && run + 0.5 * P->task_cost[(size_t)t] < target) run += P->task_cost[(size_t)t++];
+    bounds[(size_t)w] = t;
+  }
+  bounds[(size_t)n_wg] = P->n_tasks;
+  return bounds;
+}
+
+dl_status dl_set_partition(dl_problem* P, const std::vector<int64_t>& bounds) {
+  const int n_wg = (int)bounds.size() - 1;
+  if (n_wg < 0 || n_wg > P->n_wg_cap || bounds.front() != 0 || bounds.back() != P->n_tasks) {
+    dl_set_error("internal: bad partition");
+    return DL_EINVAL;
+  }
+  for (int w = 0; w < n_wg; ++w)
+    if (bounds[(size_t)w + 1] < bounds[(size_t)w]) {
+      dl_set_error("internal: partition not monotone");
+      return DL_EINVAL;
+    }
+  DL_HIP_TRY(hipMemcpyAsync(P->wg_task, bounds.data(), sizeof(int64_t) * bounds.size(), hipMemcpyHostToDevice,
+                            P->stream));
+  DL_HIP_TRY(hipStreamSynchronize(P->stream));
+  P->n_wg = n_wg;
+  return DL_OK;
+}
 
 extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** out) {
   if (!out) {

@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <utility>
 
@@ -14,7 +15,7 @@
 namespace {
 
 struct upd_args {
-  const unsigned long long* part;
+  unsigned long long* acc;  // reduced per-item sums (read and cleared)
   int n_wg;
   int mJ, J;
   double inv_q[DL_MAX_FAMILIES];
@@ -30,10 +31,27 @@ struct upd_args {
   double* grad_out; // nullable: A x - b
 };
 
-__device__ __forceinline__ double sum_partials(const unsigned long long* part, int n_wg, int mJ, int r) {
-  long long acc = 0;
-  for (int w = 0; w < n_wg; ++w) acc += (long long)part[(size_t)w * mJ + r];
-  return (double)acc;
+// First level of the partial-sum reduction: block (x, y) adds rows
+// [y*DL_RED_ROWS, (y+1)*DL_RED_ROWS) of the per-workgroup histograms for 256
+// items and adds the result into acc with a 64-bit integer atomic (exact, so
+// the total does not depend on the order).  acc is cleared by its reader.
+constexpr int DL_RED_ROWS = 16;
+__global__ void reduce_partials(const unsigned long long* __restrict__ part, int n_wg, int mJ,
+                                unsigned long long* __restrict__ acc) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mJ) return;
+  const int w0 = blockIdx.y * DL_RED_ROWS;
+  const int w1 = min(n_wg, w0 + DL_RED_ROWS);
+  long long s = 0;
+  for (int w = w0; w < w1; ++w) s += (long long)part[(size_t)w * mJ + r];
+  if (s != 0) atomicAdd(acc + r, (unsigned long long)s);
+}
+
+// Reads and clears the reduced sum of item r.
+__device__ __forceinline__ double take_sum(unsigned long long* acc, int r) {
+  const long long v = (long long)acc[r];
+  acc[r] = 0ull;
+  return (double)v;
 }
 
 // Fused accelerated step: reduce the gradient at y', take
@@ -43,7 +61,7 @@ __global__ void update_kernel(upd_args U) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= U.mJ) return;
   const int k = r / U.J;
-  const double ax = sum_partials(U.part, U.n_wg, U.mJ, r) * U.inv_q[k];
+  const double ax = take_sum(U.acc, r) * U.inv_q[k];
   const double Dr = U.D[r];
   const double gs = Dr * (ax - U.b[r]);
   const double lo = U.lam[r];
@@ -61,7 +79,7 @@ __global__ void reduce_kernel(upd_args U) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= U.mJ) return;
   const int k = r / U.J;
-  const double ax = sum_partials(U.part, U.n_wg, U.mJ, r) * U.inv_q[k];
+  const double ax = take_sum(U.acc, r) * U.inv_q[k];
   if (U.ax_out) U.ax_out[r] = ax;
   if (U.grad_out) U.grad_out[r] = ax - U.b[r];
 }
@@ -170,6 +188,15 @@ __global__ void cert_final(const double* pobj_part, int n_wg, double* out) {
 
 inline unsigned blocks_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+dl_status launch_reduce(const dl_problem* P) {
+  const int mJ = P->m * P->J;
+  if (P->n_wg <= 0) return DL_OK;
+  dim3 grid(blocks_for(mJ), (unsigned)((P->n_wg + DL_RED_ROWS - 1) / DL_RED_ROWS));
+  hipLaunchKernelGGL(reduce_partials, grid, dim3(256), 0, P->stream, P->part, P->n_wg, mJ, P->acc);
+  DL_HIP_TRY(hipGetLastError());
+  return DL_OK;
+}
+
 }  // namespace
 
 struct dl_solver {
@@ -192,7 +219,7 @@ namespace {
 upd_args make_upd(const dl_problem* P) {
   upd_args U;
   memset(&U, 0, sizeof(U));
-  U.part = P->part;
+  U.acc = P->acc;
   U.n_wg = P->n_wg;
   U.mJ = P->m * P->J;
   U.J = P->J;
@@ -219,6 +246,7 @@ dl_status certificate(dl_solver* S, dl_solve_stats* st) {
   dl_problem* P = S->P;
   const int mJ = P->m * P->J;
   DL_TRY(dl_launch_grad(P, M_HIST | M_OBJ, S->mu_lam, S->gamma, nullptr, nullptr, nullptr, P->obj_part));
+  DL_TRY(launch_reduce(P));
   upd_args U = make_upd(P);
   U.ax_out = S->ax;
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
@@ -266,6 +294,7 @@ extern "C" dl_status dl_dual_grad(dl_problem* P, const double* lambda, double ga
   DL_HIP_TRY(hipGetLastError());
   const bool want_obj = dual_obj != nullptr;
   DL_TRY(dl_launch_grad(P, want_obj ? (M_HIST | M_OBJ) : M_HIST, P->mu, gamma, nullptr, nullptr, x, P->obj_part));
+  DL_TRY(launch_reduce(P));
   upd_args U = make_upd(P);
   U.ax_out = P->lam_tmp;
   U.grad_out = grad;
@@ -321,6 +350,17 @@ extern "C" dl_status dl_solver_create(dl_problem* P, const double* lambda0, dl_s
     return fail(DL_EHIP);
   }
   *out = S;
+  return DL_OK;
+}
+
+// Device state of a solver, for the batched iteration.
+dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag) {
+  DL_CHECK_ARG(S, "NULL solver");
+  *lam = S->lam;
+  *y = S->y;
+  *mu_y = S->mu_y;
+  *mu_lam = S->mu_lam;
+  *flag = S->flag;
   return DL_OK;
 }
 
@@ -382,6 +422,7 @@ extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
       DL_HIP_TRY(hipEventRecord(eu->first, P->stream));
     }
     // FISTA momentum: t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, beta = (t_k - 1) / t_{k+1}
+    DL_TRY(launch_reduce(P));
     const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S->tk * S->tk));
     U.beta = (S->tk - 1.0) / tn;
     S->tk = tn;
@@ -436,6 +477,119 @@ extern "C" dl_status dl_solver_get_timing(dl_solver* S, dl_timing* out) {
   return DL_OK;
 }
 
+namespace {
+
+// Runs `reps` histogram passes at the solver's point with workgroup clocks on;
+// returns the mean pass time and the last pass's per-workgroup durations.
+dl_status measure_pass(dl_solver* S, int reps, double* ms, std::vector<double>* dur) {
+  dl_problem* P = S->P;
+  hipEvent_t e0, e1;
+  DL_HIP_TRY(hipEventCreate(&e0));
+  DL_HIP_TRY(hipEventCreate(&e1));
+  P->clocking = true;
+  dl_status rc = DL_OK;
+  if (hipEventRecord(e0, P->stream) != hipSuccess) rc = DL_EHIP;
+  for (int r = 0; r < reps && rc == DL_OK; ++r)
+    rc = dl_launch_grad(P, M_HIST, S->mu_y, S->gamma, nullptr, nullptr, nullptr, nullptr);
+  P->clocking = false;
+  if (rc == DL_OK && hipEventRecord(e1, P->stream) != hipSuccess) rc = DL_EHIP;
+  std::vector<unsigned long long> clk(2 * (size_t)std::max(P->n_wg, 1));
+  if (rc == DL_OK && P->n_wg > 0 &&
+      hipMemcpyAsync(clk.data(), P->wg_clock, sizeof(unsigned long long) * 2 * P->n_wg, hipMemcpyDeviceToHost,
+                     P->stream) != hipSuccess)
+    rc = DL_EHIP;
+  if (rc == DL_OK && hipStreamSynchronize(P->stream) != hipSuccess) rc = DL_EHIP;
+  float t = 0.f;
+  if (rc == DL_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = DL_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != DL_OK) {
+    dl_set_error("timing a gradient pass failed");
+    return rc;
+  }
+  *ms = t / reps;
+  dur->assign((size_t)P->n_wg, 0.0);
+  for (int w = 0; w < P->n_wg; ++w) (*dur)[(size_t)w] = (double)(clk[2 * w + 1] - clk[2 * w]);
+  return DL_OK;
+}
+
+double imbalance(const std::vector<double>& d) {
+  if (d.empty()) return 1.0;
+  double mx = 0.0, sum = 0.0;
+  for (double v : d) {
+    mx = std::max(mx, v);
+    sum += v;
+  }
+  return sum > 0 ? mx / (sum / (double)d.size()) : 1.0;
+}
+
+// New split with equal measured time: the measured cost of a workgroup's range
+// is spread evenly over its tasks and the cumulative cost is cut into equal parts.
+std::vector<int64_t> rebalance(const std::vector<int64_t>& b, const std::vector<double>& dur) {
+  const int n = (int)dur.size();
+  std::vector<double> cum((size_t)n + 1, 0.0);
+  for (int w = 0; w < n; ++w) cum[(size_t)w + 1] = cum[(size_t)w] + std::max(dur[(size_t)w], 1.0);
+  std::vector<int64_t> nb(b.size());
+  nb[0] = b[0];
+  nb[(size_t)n] = b[(size_t)n];
+  int v = 0;
+  for (int w = 1; w < n; ++w) {
+    const double target = cum[(size_t)n] * (double)w / (double)n;
+    while (v + 1 < n && cum[(size_t)v + 1] <= target) ++v;
+    const double frac = (target - cum[(size_t)v]) / (cum[(size_t)v + 1] - cum[(size_t)v]);
+    int64_t t = b[(size_t)v] + (int64_t)llround(frac * (double)(b[(size_t)v + 1] - b[(size_t)v]));
+    nb[(size_t)w] = std::max(nb[(size_t)w - 1], std::min(t, b[(size_t)n]));
+  }
+  return nb;
+}
+
+}  // namespace
+
+extern "C" dl_status dl_solver_autotune(dl_solver* S, int32_t rounds, dl_tune_result* out) {
+  DL_CHECK_ARG(S && out && rounds >= 0, "bad argument");
+  dl_problem* P = S->P;
+  memset(out, 0, sizeof(*out));
+  out->rounds = rounds;
+  if (P->n_tasks == 0) return DL_OK;
+  const int reps = 3;
+  double best_ms = 1e300;
+  std::vector<int64_t> best;
+  for (int k = 1;; k *= 2) {
+    int nw = (int)std::min<int64_t>((int64_t)P->n_cu * k, (P->n_tasks + DL_WAVES - 1) / DL_WAVES);
+    nw = std::max(1, std::min(nw, P->n_wg_cap));
+    std::vector<int64_t> b = dl_model_partition(P, nw);
+    DL_TRY(dl_set_partition(P, b));
+    double ms;
+    std::vector<double> dur;
+    DL_TRY(measure_pass(S, reps, &ms, &dur));
+    const double ms_model = ms, imb_model = imbalance(dur);
+    double cur_ms = ms, cur_imb = imb_model;
+    std::vector<int64_t> cur = b;
+    for (int r = 0; r < rounds; ++r) {
+      std::vector<int64_t> nb = rebalance(b, dur);
+      DL_TRY(dl_set_partition(P, nb));
+      DL_TRY(measure_pass(S, reps, &ms, &dur));
+      b = nb;
+      if (ms < cur_ms) {
+        cur_ms = ms;
+        cur_imb = imbalance(dur);
+        cur = nb;
+      }
+    }
+    if (cur_ms < best_ms) {
+      best_ms = cur_ms;
+      best = cur;
+      out->n_workgroups = nw;
+      out->pass_ms_model = ms_model;
+      out->imbalance_model = imb_model;
+      out->pass_ms_tuned = cur_ms;
+      out->imbalance_tuned = cur_imb;
+    }
+    if (nw >= P->n_wg_cap || (int64_t)P->n_cu * k * 2 > P->n_wg_cap) break;
+  }
+  return dl_set_partition(P, best);
+}
+
 extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const double* lambda0, double* lambda_out,
                               dl_solve_stats* st) {
   DL_CHECK_ARG(P && o && st && lambda_out, "NULL argument");
@@ -460,6 +614,15 @@ extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const doubl
     const bool last = stage == o->n_stages - 1;
     const int64_t n_it = o->iters[stage];
     int64_t done = 0;
+    if (stage == 0 && o->autotune_rounds > 0) {
+      const int64_t pre = std::min<int64_t>(n_it < 0 ? 50 : std::min<int64_t>(n_it, 50), o->max_iters);
+      rc = dl_solver_step(S, pre);
+      if (rc != DL_OK) break;
+      done = pre;
+      dl_tune_result tr;
+      rc = dl_solver_autotune(S, o->autotune_rounds, &tr);
+      if (rc != DL_OK) break;
+    }
     while ((n_it < 0 || done < n_it) && S->iters < o->max_iters) {
       int64_t chunk = (n_it < 0) ? o->max_iters - S->iters : n_it - done;
       if (last && o->check_every > 0) chunk = std::min<int64_t>(chunk, o->check_every - (done % o->check_every));
