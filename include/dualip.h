@@ -117,6 +117,14 @@ void dl_problem_destroy(dl_problem* prob);
 dl_status dl_problem_get_info(const dl_problem* prob, dl_problem_info* out);
 
 /*
+ * New day on the same eligibility pattern (the recurring solves of Section 1):
+ * replaces c (device, nnz, caller order; nullable = keep) and b (host, m*J;
+ * nullable = keep).  a, the Jacobi scaling and the step bound are unchanged.
+ * DL_EINVAL on non-finite input (c may then be partly replaced).  Synchronises.
+ */
+dl_status dl_problem_update(dl_problem* prob, const float* c, const double* b);
+
+/*
  * ObjectiveFunction.calculate (Table 1; eqs. 2-4) at lam, gamma > 0.
  *   lambda    device, m*J: the dual point (used at FP32 in the per-nnz gather)
  *   grad      device, m*J, nullable: A x*(lam) - b
@@ -242,6 +250,66 @@ typedef struct {
  * solver's iterate.  Synchronises the stream.
  */
 dl_status dl_solver_autotune(dl_solver* s, int32_t rounds, dl_tune_result* out);
+
+/* ----------------------------------------------------------------------- */
+/* Learned warm start (not part of the paper's method).                    */
+/* ----------------------------------------------------------------------- */
+/*
+ * Per-item features of a day's instance (family 0), FP32, row-major J x 16:
+ *   0 b/n, 1 log1p(n)/10, 2 mean c, 3 std c, 4 max c, 5 min c over the item's
+ *   eligible users, 6 lam_prev, 7 [lam_prev > 0], 8 b_prev/n,
+ *   9 clip(g_prev/b_prev, -1, 1), 10 10 (b/b_prev - 1), 11 n / mean n, 12-15 0
+ * with n the item's eligible-user count (n = 1 in the divisions when 0).
+ *   lam_prev  device, J: the previous day's duals
+ *   g_prev    device, J: the previous day's gradient A x - b at lam_prev
+ *   b_prev    host, J: the previous day's right-hand side
+ *   feats     device, J*16 output
+ * The per-item sums are exact integer (fixed-point) sums: reproducible.
+ */
+dl_status dl_item_features(dl_problem* prob, const double* lam_prev, const double* g_prev, const double* b_prev,
+                           float* feats);
+
+typedef struct dl_mlp dl_mlp;
+typedef struct {
+  int32_t n_in;        /* must be 16 (features zero-padded to 16) */
+  int32_t hidden;      /* H, multiple of 64 in [64, 1024] */
+  int64_t max_batch;   /* largest number of rows per call, <= 2^24 */
+  void* stream;        /* hipStream_t */
+} dl_mlp_desc;
+
+/*
+ * MLP 16 -> H -> H -> 1 with ReLU: y = relu(relu(x W1 + b1) W2 + b2) w3 + b3.
+ * FP32 master parameters, BF16 copies of W1, W2, w3 and BF16 activations for
+ * the matrix-core GEMMs, FP32 accumulation.  Parameters are flat FP32:
+ * W1 [16 x H] row-major, b1 [H], W2 [H x H] row-major, b2 [H], w3 [H], b3 [1].
+ * Created with zero parameters: set them with dl_mlp_set_params.
+ */
+dl_status dl_mlp_create(const dl_mlp_desc* desc, dl_mlp** out);
+void dl_mlp_destroy(dl_mlp* mlp);  /* NULL-safe */
+int64_t dl_mlp_num_params(const dl_mlp* mlp);
+/* host, num_params floats; resets the optimiser state (synchronises) */
+dl_status dl_mlp_set_params(dl_mlp* mlp, const float* params);
+dl_status dl_mlp_get_params(dl_mlp* mlp, float* params);  /* host; synchronises */
+/* y (device, n) = MLP(X) for X device n x 16, n <= max_batch */
+dl_status dl_mlp_forward(dl_mlp* mlp, const float* X, int64_t n, float* y);
+/* grad (device, num_params) = gradient of sum_i dy_i y_i; y (device, n, nullable) */
+dl_status dl_mlp_gradients(dl_mlp* mlp, const float* X, const float* dy, int64_t n, float* y, float* grad);
+/* One AdamW step (beta 0.9 / 0.999, eps 1e-8, decay wd on W1, W2, w3) on the
+ * loss (1/2n) sum (y - target)^2; target device, n.  loss (host, nullable)
+ * returns the loss before the step and synchronises. */
+dl_status dl_mlp_train_step(dl_mlp* mlp, const float* X, const float* target, int64_t n, float lr, float wd,
+                            double* loss);
+
+/*
+ * Judged warm start: each candidate start (device pointers, m*J each; a NULL
+ * entry means lam = 0) is clamped to lam >= 0 and scored by the dual value
+ * g_{gamma_0}(lam) at the schedule's first gamma; non-finite candidates score
+ * -inf.  dl_solve then runs from the best.  chosen (nullable) returns its index,
+ * cand_dual (host, n_cand, nullable) the scores.  Pass the cold start (NULL) as
+ * one candidate to keep it as the fallback.
+ */
+dl_status dl_solve_warm(dl_problem* prob, const dl_solve_opts* opts, int32_t n_cand, const double* const* cands,
+                        double* lambda_out, dl_solve_stats* stats, int32_t* chosen, double* cand_dual);
 
 /* Message for the last non-OK status on this thread. */
 const char* dl_last_error(void);

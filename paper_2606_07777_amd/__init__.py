@@ -115,6 +115,15 @@ class dl_tune_result(ctypes.Structure):
     ]
 
 
+class dl_mlp_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_in", ctypes.c_int32),
+        ("hidden", ctypes.c_int32),
+        ("max_batch", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 class dl_timing(ctypes.Structure):
     _fields_ = [
         ("n_grad", ctypes.c_int64),
@@ -146,6 +155,18 @@ SIGNATURES = {
     "dl_batch_destroy": ([_VP], None),
     "dl_batch_solve": ([_VP, ctypes.POINTER(dl_solve_opts), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                         ctypes.POINTER(dl_solve_stats)], _I32),
+    "dl_item_features": ([_VP, _VP, _VP, _VP, _VP], _I32),
+    "dl_problem_update": ([_VP, _VP, _VP], _I32),
+    "dl_solve_warm": ([_VP, ctypes.POINTER(dl_solve_opts), _I32, ctypes.POINTER(_VP), _VP,
+                       ctypes.POINTER(dl_solve_stats), ctypes.POINTER(_I32), _VP], _I32),
+    "dl_mlp_create": ([ctypes.POINTER(dl_mlp_desc), ctypes.POINTER(_VP)], _I32),
+    "dl_mlp_destroy": ([_VP], None),
+    "dl_mlp_num_params": ([_VP], _I64),
+    "dl_mlp_set_params": ([_VP, _VP], _I32),
+    "dl_mlp_get_params": ([_VP, _VP], _I32),
+    "dl_mlp_forward": ([_VP, _VP, _I64, _VP], _I32),
+    "dl_mlp_gradients": ([_VP, _VP, _VP, _I64, _VP, _VP], _I32),
+    "dl_mlp_train_step": ([_VP, _VP, _VP, _I64, ctypes.c_float, ctypes.c_float, ctypes.POINTER(_D)], _I32),
     "dl_last_error": ([], ctypes.c_char_p),
 }
 
@@ -288,6 +309,50 @@ class Problem:
     def solver(self, lam0=None) -> "Solver":
         return Solver(self, lam0)
 
+    def update(self, c=None, b=None):
+        """dl_problem_update: new c (caller CSR order) and / or b on the same pattern."""
+        torch = self.torch
+        ct = None if c is None else (c.to(device="cuda", dtype=torch.float32).contiguous()
+                                     if isinstance(c, torch.Tensor) else
+                                     torch.from_numpy(np.ascontiguousarray(c, dtype=np.float32)).cuda())
+        bh = None if b is None else np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+        if ct is not None and ct.numel() != self.nnz:
+            raise ValueError(f"c has {ct.numel()} entries, the problem has {self.nnz} nonzeros")
+        if bh is not None and bh.size != self.m * self.J:
+            raise ValueError(f"b has {bh.size} entries, expected {self.m * self.J}")
+        _check(load().dl_problem_update(self.handle, _ptr(ct), None if bh is None else bh.ctypes.data))
+
+    def solve_warm(self, candidates, gammas, iters, tol=1e-4, max_iters=20000, check_every=10,
+                   reset_momentum=True, step_scale=1.0, autotune_rounds=0):
+        """dl_solve_warm: returns (lam, stats, chosen index, candidate dual values)."""
+        torch = self.torch
+        g = np.ascontiguousarray(gammas, dtype=np.float64)
+        it = np.ascontiguousarray(iters, dtype=np.int64)
+        o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
+                          int(reset_momentum), int(autotune_rounds), float(step_scale))
+        ts = [None if c is None else c.to(device="cuda", dtype=torch.float64).contiguous() for c in candidates]
+        for t in ts:
+            if t is not None and t.numel() != self.m * self.J:
+                raise ValueError(f"a candidate has {t.numel()} entries, expected {self.m * self.J}")
+        arr = (ctypes.c_void_p * len(ts))(*[_ptr(t) for t in ts])
+        out = self._empty(self.m * self.J, torch.float64)
+        st = dl_solve_stats()
+        chosen = ctypes.c_int32(-1)
+        duals = np.zeros(len(ts))
+        _check(load().dl_solve_warm(self.handle, ctypes.byref(o), len(ts), arr, _ptr(out), ctypes.byref(st),
+                                    ctypes.byref(chosen), duals.ctypes.data), allow=(DL_OK, DL_NOT_CONVERGED))
+        return out, st.as_dict(), chosen.value, duals
+
+    def item_features(self, lam_prev, g_prev, b_prev):
+        """dl_item_features: [J, 16] FP32 features (family 0) on the device."""
+        torch = self.torch
+        lp = lam_prev.to(device="cuda", dtype=torch.float64).contiguous()
+        gp = g_prev.to(device="cuda", dtype=torch.float64).contiguous()
+        bp = np.ascontiguousarray(np.asarray(b_prev, dtype=np.float64).reshape(-1))
+        out = self._empty(self.J * 16, torch.float32)
+        _check(load().dl_item_features(self.handle, _ptr(lp), _ptr(gp), bp.ctypes.data, _ptr(out)))
+        return out.view(self.J, 16)
+
 
 class Solver:
     """Stepwise Maximizer (dl_solver_*)."""
@@ -382,3 +447,63 @@ class Batch:
         _check(load().dl_batch_solve(self.handle, ctypes.byref(o), l0, out_arr, stats),
                allow=(DL_OK, DL_NOT_CONVERGED))
         return outs, [s.as_dict() for s in stats]
+
+
+class MLP:
+    """dl_mlp_*: the warm-start network (16 -> H -> H -> 1) on BF16 matrix cores."""
+
+    def __init__(self, hidden: int = 256, max_batch: int = 16384, stream=None):
+        import torch
+        self.torch = torch
+        self.hidden, self.max_batch = int(hidden), int(max_batch)
+        d = dl_mlp_desc(16, self.hidden, self.max_batch, _stream(torch, stream))
+        h = ctypes.c_void_p()
+        _check(load().dl_mlp_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        self.n_params = int(load().dl_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().dl_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(load().dl_mlp_set_params(self.handle, a.ctypes.data))
+
+    def get_params(self):
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(load().dl_mlp_get_params(self.handle, a.ctypes.data))
+        return a
+
+    def forward(self, X):
+        torch = self.torch
+        X = X.to(device="cuda", dtype=torch.float32).contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check(load().dl_mlp_forward(self.handle, _ptr(X), X.shape[0], _ptr(y)))
+        return y
+
+    def gradients(self, X, dy):
+        torch = self.torch
+        X = X.to(device="cuda", dtype=torch.float32).contiguous()
+        dy = dy.to(device="cuda", dtype=torch.float32).contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(load().dl_mlp_gradients(self.handle, _ptr(X), _ptr(dy), X.shape[0], _ptr(y), _ptr(g)))
+        return y, g
+
+    def train_step(self, X, target, lr: float, wd: float = 0.0) -> float:
+        torch = self.torch
+        X = X.to(device="cuda", dtype=torch.float32).contiguous()
+        t = target.to(device="cuda", dtype=torch.float32).contiguous()
+        loss = ctypes.c_double()
+        _check(load().dl_mlp_train_step(self.handle, _ptr(X), _ptr(t), X.shape[0], float(lr), float(wd),
+                                        ctypes.byref(loss)))
+        return loss.value

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdualip.so")
-SOURCES = ["dl_problem.hip", "dl_grad.hip", "dl_solver.hip", "dl_batch.hip"]
+SOURCES = ["dl_problem.hip", "dl_grad.hip", "dl_solver.hip", "dl_batch.hip", "dl_mlp.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -107,6 +107,25 @@ __global__ void item_stats(const int32_t* idx, const void* aval, int64_t nnz, in
   }
 }
 
+// New costs on the same eligibility pattern: one wavefront per reordered user
+// copies its c row (caller order -> library order) and flags non-finite values.
+__global__ void regather_c(const int64_t* orig_rp, const int64_t* new_rp, int64_t I, const float* c_in, int bf16,
+                           void* c_out, int* flag) {
+  int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (u >= I) return;
+  int64_t os = orig_rp[u], ns = new_rp[u];
+  int64_t d = new_rp[u + 1] - ns;
+  int bad = 0;
+  for (int64_t e = lane; e < d; e += 64) {
+    float cv = c_in[os + e];
+    bad |= !isfinite(cv);
+    if (bf16) reinterpret_cast<uint16_t*>(c_out)[ns + e] = dl_f32_to_bf16_rne(cv);
+    else reinterpret_cast<float*>(c_out)[ns + e] = cv;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 template <typename T>
 dl_status dmalloc(dl_problem* P, T** p, size_t n) {
   *p = nullptr;
@@ -468,6 +487,32 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** ou
 }
 
 extern "C" void dl_problem_destroy(dl_problem* P) { free_problem(P); }
+
+extern "C" dl_status dl_problem_update(dl_problem* P, const float* c, const double* b) {
+  DL_CHECK_ARG(P, "NULL problem");
+  hipStream_t st = P->stream;
+  const int64_t mJ = (int64_t)P->m * P->J;
+  if (b)
+    for (int64_t r = 0; r < mJ; ++r) DL_CHECK_ARG(isfinite(b[r]), "b has a non-finite entry");
+  if (c && P->nnz > 0) {
+    int* flag = reinterpret_cast<int*>(P->cert_out);  // scratch int, not in use between calls
+    DL_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+    const int64_t threads = P->I * 64;
+    hipLaunchKernelGGL(regather_c, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, P->orig_rp, P->rp, P->I,
+                       c, P->storage == DL_BF16 ? 1 : 0, P->cval, flag);
+    DL_HIP_TRY(hipGetLastError());
+    int hf = 0;
+    DL_HIP_TRY(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    DL_HIP_TRY(hipStreamSynchronize(st));
+    DL_CHECK_ARG(!hf, "c has a non-finite entry (the problem's c is now partly updated)");
+  }
+  if (b) {
+    P->b_host.assign(b, b + mJ);
+    DL_HIP_TRY(hipMemcpyAsync(P->b, P->b_host.data(), sizeof(double) * mJ, hipMemcpyHostToDevice, st));
+    DL_HIP_TRY(hipStreamSynchronize(st));
+  }
+  return DL_OK;
+}
 
 extern "C" dl_status dl_problem_get_info(const dl_problem* P, dl_problem_info* o) {
   DL_CHECK_ARG(P && o, "NULL argument");

@@ -663,3 +663,63 @@ extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const doubl
   if (rc != DL_OK) return rc;
   return converged ? DL_OK : DL_NOT_CONVERGED;
 }
+
+// ---------------------------------------------------------------------------
+// Judged warm start: the candidate with the largest dual value starts the solve
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void project_candidate(const double* in, int n, double* out, int* bad) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double v = in ? in[r] : 0.0;
+  if (!isfinite(v)) atomicOr(bad, 1);
+  out[r] = isfinite(v) ? fmax(v, 0.0) : 0.0;
+}
+}  // namespace
+
+extern "C" dl_status dl_solve_warm(dl_problem* P, const dl_solve_opts* o, int32_t n_cand,
+                                   const double* const* cands, double* lambda_out, dl_solve_stats* stats,
+                                   int32_t* chosen, double* cand_dual) {
+  DL_CHECK_ARG(P && o && stats && lambda_out && n_cand >= 1 && cands, "bad argument");
+  DL_CHECK_ARG(o->n_stages >= 1 && o->gammas, "empty schedule");
+  const int mJ = P->m * P->J;
+  const double gamma0 = o->gammas[0];
+  double* tmp = nullptr;
+  int* bad = nullptr;
+  DL_HIP_TRY(hipMalloc((void**)&tmp, sizeof(double) * (size_t)mJ * 2 + sizeof(int)));
+  bad = reinterpret_cast<int*>(tmp + 2 * (size_t)mJ);
+  double* grad = tmp + mJ;
+  int best = -1;
+  double best_g = -INFINITY;
+  dl_status rc = DL_OK;
+  for (int q = 0; q < n_cand && rc == DL_OK; ++q) {
+    if (hipMemsetAsync(bad, 0, sizeof(int), P->stream) != hipSuccess) { rc = DL_EHIP; break; }
+    hipLaunchKernelGGL(project_candidate, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, cands[q], mJ, tmp, bad);
+    double g = -INFINITY;
+    rc = dl_dual_grad(P, tmp, gamma0, grad, &g, nullptr);
+    if (rc != DL_OK) break;
+    int hb = 0;
+    if (hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess) { rc = DL_EHIP; break; }
+    if (hb || !isfinite(g)) g = -INFINITY;  // a non-finite candidate never wins
+    if (cand_dual) cand_dual[q] = g;
+    if (g > best_g) {
+      best_g = g;
+      best = q;
+    }
+  }
+  if (rc == DL_OK && best < 0) {
+    dl_set_error("no finite candidate start");
+    rc = DL_NUMERIC;
+  }
+  if (rc == DL_OK) {
+    hipLaunchKernelGGL(project_candidate, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, cands[best], mJ, tmp, bad);
+    if (hipGetLastError() != hipSuccess) rc = DL_EHIP;
+  }
+  dl_status sr = rc;
+  if (rc == DL_OK) sr = dl_solve(P, o, tmp, lambda_out, stats);
+  (void)hipStreamSynchronize(P->stream);
+  (void)hipFree(tmp);
+  if (chosen) *chosen = best;
+  return sr;
+}
