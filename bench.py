@@ -76,7 +76,7 @@ def cpu_baseline(inst, budget_s: float):
     t = time.time()
     oracle.solve(sample, [1e-2], [1], jacobi=True, check_every=0)
     one = time.time() - t
-    iters = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    iters = max(1, min(200, int(budget_s / max(one, 1e-3))))
     t = time.time()
     oracle.solve(sample, [1e-2], [iters], jacobi=True, check_every=0)
     el = time.time() - t
@@ -84,6 +84,63 @@ def cpu_baseline(inst, budget_s: float):
     return {"value": rate, "unit": "nnz*iter/s", "cores": threads, "kind": "oracle",
             "sample": f"first {S} users ({sample.nnz} nnz) of the same instance, b scaled by {S}/{inst.n_users}, "
                       f"{iters} FP64 iterations in {el:.1f}s"}
+
+
+def learned_eval(args, log=log):
+    """Time to a 1e-4 certified gap on drifting days: cold start over the
+    continuation schedule, the previous day's duals at the final gamma, and the
+    judged learned start ({learned, previous, cold} at the final gamma).  Times
+    include the learned path's gradient pass, feature pass and network."""
+    import numpy as np
+    import torch
+
+    import paper_2606_07777_amd as dl
+    import workloads as wl
+    from paper_2606_07777_amd.learned import WarmStart
+    cold = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[300, 300, -1], tol=1e-4, max_iters=20000, check_every=10)
+    final = dict(gammas=[1e-3], iters=[-1], tol=1e-4, max_iters=20000, check_every=10)
+    ws = WarmStart.load(args.learned)
+    days = []
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    for ch in range(args.eval_chains):
+        chain = 6000 + ch
+        inst = wl.cadence_base(chain, n_users=args.eval_users, n_items=args.eval_items)
+        prob = dl.Problem.from_instance(inst)
+        (lam, st), t = timed(lambda: prob.solve(**cold))
+        log(f"eval chain {chain} day 0: cold {st['iters']} iterations, {t:.2f}s, gap {st['rel_gap']:.1e}")
+        for d in range(1, args.eval_days + 1):
+            today = wl.cadence_next(inst, d)
+            prob.update(c=today.c, b=today.b)
+            (lc, sc), tc = timed(lambda: prob.solve(**cold))
+            (lp, sp), tp = timed(lambda: prob.solve(lam0=lam, **final))
+            (ll, sl, info), tl = timed(lambda: ws.solve(prob, lam, inst.b, **final))
+            rec = {"chain": chain, "day": d,
+                   "cold": {"s": tc, "iters": sc["iters"], "gap": sc["rel_gap"], "status": sc["status"]},
+                   "previous": {"s": tp, "iters": sp["iters"], "gap": sp["rel_gap"], "status": sp["status"]},
+                   "learned": {"s": tl, "iters": sl["iters"], "gap": sl["rel_gap"], "status": sl["status"],
+                               "chosen": info["chosen"], "predict_s": info["predict_s"]}}
+            days.append(rec)
+            log(f"eval chain {chain} day {d}: cold {sc['iters']} it {tc:.2f}s | previous {sp['iters']} it "
+                f"{tp:.2f}s | learned ({info['chosen']}) {sl['iters']} it {tl:.2f}s")
+            inst, lam = today, ll
+        del prob
+    def mean(k, f):
+        return float(np.mean([r[k][f] for r in days]))
+    return {"workload": f"drifting days of a {args.eval_users} x {args.eval_items} matching instance "
+                        f"(Poisson(10) degrees, c=-U(0,1), binding b=0.5 I/J; c, b drift 5%/day)",
+            "chains": args.eval_chains, "days_per_chain": args.eval_days, "weights": os.path.relpath(args.learned, ROOT),
+            "mean_s": {k: mean(k, "s") for k in ("cold", "previous", "learned")},
+            "mean_iters": {k: mean(k, "iters") for k in ("cold", "previous", "learned")},
+            "speedup_learned_vs_cold": mean("cold", "s") / max(mean("learned", "s"), 1e-12),
+            "speedup_learned_vs_previous": mean("previous", "s") / max(mean("learned", "s"), 1e-12),
+            "days": days}
 
 
 def main():
@@ -102,6 +159,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--solve", action="store_true", help="also time a cold solve to a 1e-4 certified gap")
+    ap.add_argument("--learned", default=os.path.join(ROOT, "paper_2606_07777_amd", "weights", "warmstart.npz"),
+                    help="warm-start network for the time-to-gap comparison ('' = skip)")
+    ap.add_argument("--eval-users", type=int, default=10_000_000)
+    ap.add_argument("--eval-items", type=int, default=10_000)
+    ap.add_argument("--eval-chains", type=int, default=1)
+    ap.add_argument("--eval-days", type=int, default=3)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -189,9 +252,13 @@ def main():
         t0 = time.perf_counter()
         lam, st = prob.solve([1e-1, 1e-2, 1e-3], [300, 300, -1], tol=1e-4, max_iters=20000, check_every=10)
         torch.cuda.synchronize()
-        out["time_to_gap"] = {"cold_s": time.perf_counter() - t0, "iters": st["iters"], "rel_gap": st["rel_gap"],
+        out["cold_solve_production"] = {"cold_s": time.perf_counter() - t0, "iters": st["iters"], "rel_gap": st["rel_gap"],
                               "status": st["status"], "schedule": "gamma 1e-1,1e-2 (300 each) then 1e-3 to 1e-4 gap"}
-        log(f"cold solve: {out['time_to_gap']}")
+        log(f"cold solve: {out['cold_solve_production']}")
+    if args.learned and os.path.exists(args.learned):
+        del prob
+        torch.cuda.empty_cache()
+        out["time_to_gap"] = learned_eval(args)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget)

@@ -261,7 +261,10 @@ dl_status dl_solver_autotune(dl_solver* s, int32_t rounds, dl_tune_result* out);
  *   9 clip(g_prev/b_prev, -1, 1), 10 10 (b/b_prev - 1), 11 n / mean n, 12-15 0
  * with n the item's eligible-user count (n = 1 in the divisions when 0).
  *   lam_prev  device, J: the previous day's duals
- *   g_prev    device, J: the previous day's gradient A x - b at lam_prev
+ *   g_prev    device, J: a gradient A x - b at lam_prev; the warm-start
+ *             pipeline passes this problem's (today's) gradient there, so
+ *             column 9 is today's relative over-subscription at yesterday's
+ *             duals
  *   b_prev    host, J: the previous day's right-hand side
  *   feats     device, J*16 output
  * The per-item sums are exact integer (fixed-point) sums: reproducible.
@@ -290,8 +293,20 @@ int64_t dl_mlp_num_params(const dl_mlp* mlp);
 /* host, num_params floats; resets the optimiser state (synchronises) */
 dl_status dl_mlp_set_params(dl_mlp* mlp, const float* params);
 dl_status dl_mlp_get_params(dl_mlp* mlp, float* params);  /* host; synchronises */
+/*
+ * Input normalisation (host, 16 each): the network sees column k of X as
+ * (x - shift[k]) * scale[k] (FP32, then one BF16 rounding); scale 0 removes
+ * a column.  Default shift 0, scale 1.  Synchronises.
+ */
+dl_status dl_mlp_set_input_norm(dl_mlp* mlp, const float* shift, const float* scale);
 /* y (device, n) = MLP(X) for X device n x 16, n <= max_batch */
 dl_status dl_mlp_forward(dl_mlp* mlp, const float* X, int64_t n, float* y);
+/*
+ * Warm-start prediction: lam0 (device, n) = max(0, lam_prev + s * MLP(X)) in
+ * FP64; rows whose network output is non-finite keep max(0, lam_prev).
+ */
+dl_status dl_mlp_predict_duals(dl_mlp* mlp, const float* X, int64_t n, const double* lam_prev, double s,
+                               double* lam0);
 /* grad (device, num_params) = gradient of sum_i dy_i y_i; y (device, n, nullable) */
 dl_status dl_mlp_gradients(dl_mlp* mlp, const float* X, const float* dy, int64_t n, float* y, float* grad);
 /* One AdamW step (beta 0.9 / 0.999, eps 1e-8, decay wd on W1, W2, w3) on the

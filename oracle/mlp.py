@@ -109,7 +109,9 @@ def item_features(inst, lam_prev, slack_prev, b_prev) -> np.ndarray:
     """[J, 16] features of every item (one family), FP64, columns:
     0 b/n, 1 log1p(n)/10, 2 mean c, 3 std c, 4 max c, 5 min c over the item's
     eligible users, 6 lam_prev, 7 [lam_prev > 0], 8 b_prev/n,
-    9 clip(g_prev/b_prev, -1, 1) (yesterday's relative slack at its duals),
+    9 clip(g_prev/b_prev, -1, 1) with g_prev a gradient A x - b taken at
+    lam_prev (the warm-start pipeline uses today's instance there, giving
+    today's relative over-subscription at yesterday's duals),
     10 10 (b/b_prev - 1), 11 n / mean n; 12..15 zero.  Items with no eligible
     user get n = 0 and c statistics 0."""
     J = inst.n_items

@@ -156,6 +156,8 @@ SIGNATURES = {
     "dl_batch_solve": ([_VP, ctypes.POINTER(dl_solve_opts), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                         ctypes.POINTER(dl_solve_stats)], _I32),
     "dl_item_features": ([_VP, _VP, _VP, _VP, _VP], _I32),
+    "dl_mlp_set_input_norm": ([_VP, _VP, _VP], _I32),
+    "dl_mlp_predict_duals": ([_VP, _VP, _I64, _VP, ctypes.c_double, _VP], _I32),
     "dl_problem_update": ([_VP, _VP, _VP], _I32),
     "dl_solve_warm": ([_VP, ctypes.POINTER(dl_solve_opts), _I32, ctypes.POINTER(_VP), _VP,
                        ctypes.POINTER(dl_solve_stats), ctypes.POINTER(_I32), _VP], _I32),
@@ -483,6 +485,22 @@ class MLP:
         _check(load().dl_mlp_get_params(self.handle, a.ctypes.data))
         return a
 
+    def set_input_norm(self, shift, scale):
+        sh = np.ascontiguousarray(shift, dtype=np.float32).reshape(16)
+        sc = np.ascontiguousarray(scale, dtype=np.float32).reshape(16)
+        _check(load().dl_mlp_set_input_norm(self.handle, sh.ctypes.data, sc.ctypes.data))
+
+    def predict_duals(self, X, lam_prev, s: float):
+        """max(0, lam_prev + s * MLP(X)) in FP64 on the device."""
+        torch = self.torch
+        X = X.to(device="cuda", dtype=torch.float32).contiguous()
+        lp = lam_prev.to(device="cuda", dtype=torch.float64).contiguous()
+        if lp.numel() != X.shape[0]:
+            raise ValueError("lam_prev must have one entry per row of X")
+        out = torch.empty(X.shape[0], dtype=torch.float64, device="cuda")
+        _check(load().dl_mlp_predict_duals(self.handle, _ptr(X), X.shape[0], _ptr(lp), float(s), _ptr(out)))
+        return out
+
     def forward(self, X):
         torch = self.torch
         X = X.to(device="cuda", dtype=torch.float32).contiguous()
@@ -499,11 +517,14 @@ class MLP:
         _check(load().dl_mlp_gradients(self.handle, _ptr(X), _ptr(dy), X.shape[0], _ptr(y), _ptr(g)))
         return y, g
 
-    def train_step(self, X, target, lr: float, wd: float = 0.0) -> float:
+    def train_step(self, X, target, lr: float, wd: float = 0.0, want_loss: bool = True):
+        """One AdamW step; returns the loss before it (synchronising) or None."""
         torch = self.torch
         X = X.to(device="cuda", dtype=torch.float32).contiguous()
         t = target.to(device="cuda", dtype=torch.float32).contiguous()
+        if X.shape[0] > self.max_batch or t.numel() != X.shape[0]:
+            raise ValueError("batch larger than max_batch or target of the wrong length")
         loss = ctypes.c_double()
         _check(load().dl_mlp_train_step(self.handle, _ptr(X), _ptr(t), X.shape[0], float(lr), float(wd),
-                                        ctypes.byref(loss)))
-        return loss.value
+                                        ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None

@@ -99,6 +99,27 @@ __global__ void to_bf16(const float* __restrict__ in, int64_t n, uint16_t* __res
   if (i < n) out[i] = dl_f32_to_bf16_rne(in[i]);
 }
 
+// Network input: column k of X becomes (x - shift[k]) * scale[k], rounded once to BF16.
+__global__ void input_to_bf16(const float* __restrict__ X, int64_t n16, const float* __restrict__ norm,
+                              uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n16) return;
+  const int k = (int)(i & 15);
+  const float v = (X[i] - norm[k]) * norm[16 + k];
+  out[i] = dl_f32_to_bf16_rne(v);
+}
+
+// Predicted duals: lam0 = max(0, lam_prev + s y), with a non-finite y giving
+// lam_prev (the prediction then falls back to the previous day's value).
+__global__ void predict_duals(const float* __restrict__ y, const double* __restrict__ lam_prev, int64_t n, double s,
+                              double* __restrict__ lam0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double yi = (double)y[i];
+  const double v = isfinite(yi) ? lam_prev[i] + s * yi : lam_prev[i];
+  lam0[i] = fmax(v, 0.0);
+}
+
 // W3 (H) as an H x 16 BF16 matrix with the weights in column 0.
 __global__ void pack_w3(const float* __restrict__ w3, int H, uint16_t* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -271,6 +292,7 @@ struct dl_mlp {
   uint16_t *W1b = nullptr, *W2b = nullptr, *W3b = nullptr;
   uint16_t *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dH2b = nullptr, *dH1b = nullptr, *dyb = nullptr;
   float *dH2 = nullptr, *dH1 = nullptr, *y = nullptr, *dy = nullptr, *Cp = nullptr, *colpart = nullptr, *tmp = nullptr;
+  float* norm = nullptr;  // [16 shifts, 16 scales] of the network input
   size_t cp_cap = 0;
   double* loss_dev = nullptr;
   double* loss_host = nullptr;
@@ -282,7 +304,7 @@ namespace {
 void free_mlp(dl_mlp* N) {
   if (!N) return;
   void* ptrs[] = {N->P, N->G, N->Mo, N->Vo, N->decay, N->W1b, N->W2b, N->W3b, N->Xb, N->H1b, N->H2b, N->dH2b,
-                  N->dH1b, N->dyb, N->dH2, N->dH1, N->y, N->dy, N->Cp, N->colpart, N->tmp, N->loss_dev};
+                  N->dH1b, N->dyb, N->dH2, N->dH1, N->y, N->dy, N->Cp, N->colpart, N->tmp, N->loss_dev, N->norm};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (N->loss_host) (void)hipHostFree(N->loss_host);
@@ -335,7 +357,7 @@ dl_status refresh_bf16(dl_mlp* N) {
 
 dl_status forward_impl(dl_mlp* N, const float* X, int64_t n) {
   const int H = N->H;
-  hipLaunchKernelGGL(to_bf16, dim3(nblk(n * 16)), dim3(256), 0, N->stream, X, n * 16, N->Xb);
+  hipLaunchKernelGGL(input_to_bf16, dim3(nblk(n * 16)), dim3(256), 0, N->stream, X, n * 16, N->norm, N->Xb);
   DL_HIP_TRY(hipGetLastError());
   DL_TRY(gemm(N, false, false, N->Xb, 16, N->W1b, H, (int)n, H, 16, H, N->P + N->off_b1, 1, nullptr, nullptr, N->H1b,
               16));
@@ -414,7 +436,7 @@ extern "C" dl_status dl_mlp_create(const dl_mlp_desc* d, dl_mlp** out) {
             dal(&N->dH2, n * H) == hipSuccess && dal(&N->dH1, n * H) == hipSuccess && dal(&N->y, n) == hipSuccess &&
             dal(&N->dy, n) == hipSuccess && dal(&N->Cp, N->cp_cap) == hipSuccess &&
             dal(&N->colpart, 64 * H) == hipSuccess && dal(&N->tmp, n * 16) == hipSuccess &&
-            dal(&N->loss_dev, 1) == hipSuccess && hipHostMalloc((void**)&N->loss_host, sizeof(double)) == hipSuccess;
+            dal(&N->loss_dev, 1) == hipSuccess && dal(&N->norm, 32) == hipSuccess && hipHostMalloc((void**)&N->loss_host, sizeof(double)) == hipSuccess;
   if (!ok) {
     free_mlp(N);
     dl_set_error("device allocation failed");
@@ -425,7 +447,10 @@ extern "C" dl_status dl_mlp_create(const dl_mlp_desc* d, dl_mlp** out) {
   for (int64_t i = N->off_W2; i < N->off_b2; ++i) dec[(size_t)i] = 1;
   for (int64_t i = N->off_w3; i < N->off_b3; ++i) dec[(size_t)i] = 1;
   hipStream_t st = N->stream;
+  const float norm0[32] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                           1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
   if (hipMemcpyAsync(N->decay, dec.data(), dec.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(N->norm, norm0, sizeof(norm0), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemsetAsync(N->P, 0, sizeof(float) * N->n_params, st) != hipSuccess ||
       hipMemsetAsync(N->Mo, 0, sizeof(float) * N->n_params, st) != hipSuccess ||
       hipMemsetAsync(N->Vo, 0, sizeof(float) * N->n_params, st) != hipSuccess ||
@@ -462,6 +487,31 @@ extern "C" dl_status dl_mlp_get_params(dl_mlp* N, float* host) {
   DL_CHECK_ARG(N && host, "NULL argument");
   DL_HIP_TRY(hipMemcpyAsync(host, N->P, sizeof(float) * N->n_params, hipMemcpyDeviceToHost, N->stream));
   DL_HIP_TRY(hipStreamSynchronize(N->stream));
+  return DL_OK;
+}
+
+extern "C" dl_status dl_mlp_set_input_norm(dl_mlp* N, const float* shift, const float* scale) {
+  DL_CHECK_ARG(N && shift && scale, "NULL argument");
+  float h[32];
+  for (int k = 0; k < 16; ++k) {
+    DL_CHECK_ARG(isfinite(shift[k]) && isfinite(scale[k]), "non-finite input normalisation");
+    h[k] = shift[k];
+    h[16 + k] = scale[k];
+  }
+  DL_HIP_TRY(hipMemcpyAsync(N->norm, h, sizeof(h), hipMemcpyHostToDevice, N->stream));
+  DL_HIP_TRY(hipStreamSynchronize(N->stream));
+  return DL_OK;
+}
+
+extern "C" dl_status dl_mlp_predict_duals(dl_mlp* N, const float* X, int64_t n, const double* lam_prev, double s,
+                                          double* lam0) {
+  DL_CHECK_ARG(N && (n == 0 || (X && lam_prev && lam0)), "NULL argument");
+  DL_CHECK_ARG(n >= 0 && n <= N->max_batch, "n exceeds max_batch");
+  DL_CHECK_ARG(isfinite(s), "non-finite scale");
+  if (n == 0) return DL_OK;
+  DL_TRY(forward_impl(N, X, n));
+  hipLaunchKernelGGL(predict_duals, dim3(nblk(n)), dim3(256), 0, N->stream, N->y, lam_prev, n, s, lam0);
+  DL_HIP_TRY(hipGetLastError());
   return DL_OK;
 }
 

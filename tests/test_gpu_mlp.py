@@ -133,3 +133,27 @@ def test_item_features_match_oracle(dl, orc, wl):
     F = prob.item_features(torch.from_numpy(lam_prev), torch.from_numpy(g_prev), b_prev).cpu().numpy()
     Fo = om.item_features(inst, lam_prev, g_prev, b_prev)
     np.testing.assert_allclose(F, Fo, rtol=2e-6, atol=2e-7)
+
+
+def test_input_norm_and_predicted_duals(dl, orc):
+    """Normalised input (x - shift) * scale in FP32 then BF16, with a zero scale
+    removing a column; lam0 = max(0, lam_prev + s y) against the oracle forward
+    on the same normalised, rounded input."""
+    import torch
+    net, om, q, X, Xr, torch = _setup(dl, orc, 256, 1500, seed=3)
+    rng = np.random.default_rng(11)
+    shift = rng.normal(size=16).astype(np.float32)
+    scale = rng.uniform(0.5, 2.0, size=16).astype(np.float32)
+    scale[[1, 4, 5]] = 0.0
+    net.set_input_norm(shift, scale)
+    Xn = (X - shift[None, :]) * scale[None, :]  # FP32, same two roundings as the kernel
+    yo, _ = om.forward(q, orc.bf16_round(Xn).astype(np.float64))
+    y = net.forward(torch.from_numpy(X)).cpu().numpy()
+    print(f"normalised forward rel {rel(y, yo):.2e}")
+    assert rel(y, yo) <= 5e-3
+    lam_prev = np.maximum(0.0, rng.normal(size=X.shape[0]) * 0.1)
+    s = 0.037
+    lam0 = net.predict_duals(torch.from_numpy(X), torch.from_numpy(lam_prev), s).cpu().numpy()
+    # same network output as forward; the FP64 epilogue may fuse the multiply-add
+    np.testing.assert_allclose(lam0, np.maximum(0.0, lam_prev + s * y.astype(np.float64)), rtol=1e-15, atol=1e-17)
+    assert (lam0 >= 0).all() and (lam0 == 0).any() and (lam0 > 0).any()
