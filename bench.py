@@ -73,10 +73,14 @@ def cpu_baseline(inst, budget_s: float):
     sample = inst.user_slice(0, S)
     # b scaled with the sample so the capacities keep binding
     sample.b = inst.b * (S / inst.n_users)
+    # marginal cost of an iteration: one call of 1 iteration and one of 3
     t = time.time()
     oracle.solve(sample, [1e-2], [1], jacobi=True, check_every=0)
-    one = time.time() - t
-    iters = max(1, min(200, int(budget_s / max(one, 1e-3))))
+    t1 = time.time() - t
+    t = time.time()
+    oracle.solve(sample, [1e-2], [3], jacobi=True, check_every=0)
+    per = max((time.time() - t - t1) / 2, 1e-3)
+    iters = max(1, min(300, int(budget_s / per)))
     t = time.time()
     oracle.solve(sample, [1e-2], [iters], jacobi=True, check_every=0)
     el = time.time() - t
@@ -143,12 +147,61 @@ def learned_eval(args, log=log):
             "days": days}
 
 
+def batch_bench(args):
+    """The uneven batch: 64 instances (users log-uniform in [5e4, 2e6], items
+    log-uniform in [100, 5000], degree round(lognormal(3.5, 0.8)), uniform items,
+    c = -U(0,1), a = 1, binding b = 0.5 I/J, simplex <= 1) solved to a 1e-4 gap
+    (gamma 1e-1, 1e-2 for 300 iterations each, then 1e-3), once as one batch
+    (one launch per iteration phase for all live members) and once as 64
+    sequential solo solves.  Prints its own JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2606_07777_amd as dl
+    import workloads as wl
+    t = time.time()
+    members = [wl.batch_member(k, binding=True, scale=args.batch_scale) for k in range(args.batch_n)]
+    nnz = [m.nnz for m in members]
+    log(f"generated {len(members)} members, {sum(nnz)} nnz, {sum(m.n_users for m in members)} users "
+        f"in {time.time() - t:.1f}s")
+    torch.cuda.set_device(0)
+    probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]
+    sched = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[300, 300, -1], tol=1e-4, max_iters=20000, check_every=10)
+    batch = dl.Batch(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam_b, st_b = batch.solve(**sched)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batch: {t_batch:.2f}s, iterations {min(s['iters'] for s in st_b)}..{max(s['iters'] for s in st_b)}")
+    t0 = time.perf_counter()
+    st_s = []
+    for p in probs:
+        st_s.append(p.solve(**sched)[1])
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    log(f"solo: {t_solo:.2f}s")
+    work_b = sum(n * s["iters"] for n, s in zip(nnz, st_b))
+    work_s = sum(n * s["iters"] for n, s in zip(nnz, st_s))
+    same = all(a["iters"] == b["iters"] for a, b in zip(st_b, st_s))
+    out = {"metric": "time to a 1e-4 gap for every member of the uneven batch", "unit": "s",
+           "batch_s": t_batch, "solo_sequential_s": t_solo, "speedup": t_solo / t_batch,
+           "batch_nnz_iter_per_s": work_b / t_batch, "solo_nnz_iter_per_s": work_s / t_solo,
+           "same_iterations_as_solo": same, "members": len(members), "nnz": int(sum(nnz)),
+           "converged": int(sum(s["status"] == 0 for s in st_b)),
+           "max_rel_gap": float(max(s["rel_gap"] for s in st_b)),
+           "config": {"workload": f"uneven batch of {len(members)} (users scale {args.batch_scale})"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="production", choices=["production", "tiny"])
+    ap.add_argument("--workload", default="production", choices=["production", "tiny", "batch"])
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--users", type=int, default=10_000_000)
     ap.add_argument("--items", type=int, default=10_000)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"])
@@ -171,6 +224,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "batch":
+        return batch_bench(args)
 
     import numpy as np
     import torch

@@ -51,6 +51,12 @@ constexpr int DL_MAX_FAMILIES = 4;
 #define DL_KMAX_PLAIN 12
 #endif
 constexpr int DL_KMAX_A = 8;
+// Element loops of the group path step in chunks: loads in chunks of 4, the
+// arithmetic in chunks of DL_CHUNK (a divisor of 4); a chunk runs when its
+// first element is below the task's per-lane count.
+#ifndef DL_CHUNK
+#define DL_CHUNK 4
+#endif
 // Elements of zero padding after idx, c and every stored a family: a group of
 // lanes may read up to 64*KMAX + 63 elements past a row start without
 // predication, and masks what lies past the row.

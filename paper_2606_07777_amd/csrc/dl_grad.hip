@@ -119,6 +119,13 @@ __device__ __forceinline__ void hist_add(unsigned long long* h, int r, float w, 
   if (q != 0) atomicAdd(h + r, (unsigned long long)(long long)q);
 }
 
+// w >= 0 (families with a == 1): rounds half up with one fused multiply-add and
+// a truncating convert; the 64-bit addend has a zero high word.
+__device__ __forceinline__ void hist_add_pos(unsigned long long* h, int r, float w, float qs) {
+  const uint32_t q = __float2uint_rz(fmaf(w, qs, 0.5f));
+  if (q != 0) atomicAdd(h + r, (unsigned long long)q);
+}
+
 // ---------------------------------------------------------------------------
 // Group path: 2^GLOG lanes per user, up to KMAX elements per lane.
 // ---------------------------------------------------------------------------
@@ -129,6 +136,14 @@ __device__ __forceinline__ void hist_add(unsigned long long* h, int r, float w, 
   _Pragma("unroll") for (int kc_ = 0; kc_ < (KMAX); kc_ += 4)  \
     if (kc_ < (K))                                             \
       _Pragma("unroll") for (int k = kc_; k < kc_ + 4; ++k)
+// Arithmetic loops: chunks of DL_CHUNK, or of 2 with stored a (whose larger
+// register set would otherwise spill in the batched kernel).
+template <bool HAS_A>
+constexpr int chunk_of() { return HAS_A ? 2 : DL_CHUNK; }
+#define DL_FOR_KC(k, KMAX, K)                                                             \
+  _Pragma("unroll") for (int kc_ = 0; kc_ < (KMAX); kc_ += chunk_of<HAS_A>())             \
+    if (kc_ < (K))                                                                        \
+      _Pragma("unroll") for (int k = kc_; k < kc_ + chunk_of<HAS_A>(); ++k)
 
 struct TaskMeta {
   int64_t s;   // row start (0 for lanes without a user)
@@ -198,7 +213,7 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
   constexpr int G = 1 << GLOG;
   K = __builtin_amdgcn_readfirstlane(K);
   const int d = (int)(m.e - m.s);
-  DL_FOR_K(k, KMAX, K) {
+  DL_FOR_KC(k, KMAX, K) {
     {
       const bool in = lid + k * G < d;
       float val;
@@ -240,7 +255,7 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   if (!box) {
     // pass A: largest two entries, positive part and its count
     float m1 = -INFINITY, m2 = -INFINITY, sp = 0.f, cp = 0.f;
-    DL_FOR_K(k, KMAX, K) {
+    DL_FOR_KC(k, KMAX, K) {
       {
         m2 = fmaxf(m2, fminf(m1, v[k]));
         m1 = fmaxf(m1, v[k]);
@@ -265,7 +280,7 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
     }
     for (int it = 0; it < 64 && __any(!done); ++it) {
       float f = 0.f, cnt = 0.f, mina = INFINITY;
-      DL_FOR_K(k, KMAX, K) {
+      DL_FOR_KC(k, KMAX, K) {
         {
           const float t = v[k] - theta;
           f += fmaxf(t, 0.f);
@@ -288,9 +303,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   }
 
   float lobj = 0.f;
-  DL_FOR_K(k, KMAX, K) {
+  auto emit = [&](int k, float x) {
     {
-      const float x = box ? fminf(fmaxf(v[k], 0.f), z) : fmaxf(v[k] - theta, 0.f);
       if constexpr ((MODE & M_XOUT) != 0) {
         if (lid + k * G < (int)(m.e - m.s)) A.x_out[m.os + lid + k * G] = x;
       }
@@ -302,7 +316,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
             if constexpr (HAS_A) {
               if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
             }
-            hist_add(s_hist, f * A.J + R.j[k], w, A.qscale[f]);
+            if constexpr (HAS_A) hist_add(s_hist, f * A.J + R.j[k], w, A.qscale[f]);
+            else hist_add_pos(s_hist, f * A.J + R.j[k], w, A.qscale[f]);
           }
         }
       }
@@ -315,6 +330,12 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
         lobj += xt * fmaf(0.5f * A.gamma, xt, cc[k]);
       }
     }
+  };
+  // one loop per projection kind, so the kind is not re-tested per element
+  if (box) {
+    DL_FOR_KC(k, KMAX, K) emit(k, fminf(fmaxf(v[k], 0.f), z));
+  } else {
+    DL_FOR_KC(k, KMAX, K) emit(k, fmaxf(v[k] - theta, 0.f));
   }
   if (MODE & (M_OBJ | M_REPAIR)) acc += (double)lobj;
 }
@@ -465,7 +486,8 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
       for (int f = 0; f < MF; ++f) {
         if (f < A.m) {
           float w = (HAS_A && A.a_slot[f] >= 0) ? af[HAS_A ? f : 0] * x : x;
-          hist_add(s_hist, f * A.J + j, w, A.qscale[f]);
+          if constexpr (HAS_A) hist_add(s_hist, f * A.J + j, w, A.qscale[f]);
+          else hist_add_pos(s_hist, f * A.J + j, w, A.qscale[f]);
         }
       }
     }
