@@ -56,7 +56,7 @@ def measured_traffic(args):
     """HBM bytes per gradient pass from the committed rocprofv3 counter summary, when it
     was taken on the current kernel source and this workload; otherwise None."""
     path = os.path.join(ROOT, "profiles", "grad_pass_production_traffic.json")
-    if not os.path.exists(path) or args.workload != "production" or args.storage != "f32":
+    if not os.path.exists(path) or args.workload != "production" or args.storage != "f32" or args.layout != "bucketed":
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha1") != kernel_source_hash():
@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--users", type=int, default=10_000_000)
     ap.add_argument("--items", type=int, default=10_000)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--layout", default="bucketed", choices=["bucketed", "wavefront"],
+                    help="user-to-lane mapping; wavefront = one wavefront per user (baseline layout)")
     ap.add_argument("--wg-per-cu", type=int, default=8, help="largest workgroups-per-CU grid the tuner may pick")
     ap.add_argument("--tune-rounds", type=int, default=3, help="workgroup-split balancing rounds (0 = off)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
@@ -244,7 +246,8 @@ def main():
         del src, dst
         log(f"reference copy: {args.copy_ref_mb} MiB read, {args.copy_ref_mb} MiB written")
     t = time.time()
-    prob = dl.Problem.from_instance(inst, storage=args.storage, jacobi=True, wg_per_cu=args.wg_per_cu)
+    prob = dl.Problem.from_instance(inst, storage=args.storage, jacobi=True, wg_per_cu=args.wg_per_cu,
+                                    layout=args.layout)
     torch.cuda.synchronize()
     info = prob.info()
     log(f"problem created in {time.time() - t:.1f}s: {info['n_workgroups']} workgroups, {info['n_tasks']} tasks, "
@@ -295,7 +298,8 @@ def main():
         "dtype": "f32" if args.storage == "f32" else "bf16-storage/f32",
         "data": "synthetic",
         "config": {"workload": desc, "n_users": inst.n_users, "n_items": inst.n_items, "nnz": inst.nnz,
-                   "storage": args.storage, "gamma_timed": 1e-2, "parallelism": "single GPU"},
+                   "storage": args.storage, "layout": args.layout, "gamma_timed": 1e-2,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args),
                      "kernel": "grad_pass", "kernel_ms": grad_ms, "bytes_per_pass": bytes_pass},

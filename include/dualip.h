@@ -66,6 +66,17 @@ typedef struct dl_problem dl_problem;
 typedef struct dl_solver dl_solver;
 typedef struct dl_batch dl_batch;
 
+/*
+ * User-to-lane mapping of the gradient pass.  DL_LAYOUT_BUCKETED groups users
+ * by degree and gives each 2^g lanes so that no lane holds more than a fixed
+ * number of elements (the degree bucketing of Section 4.2, generalised).
+ * DL_LAYOUT_WAVEFRONT gives every user a full 64-lane wavefront: the plain
+ * mapping, kept as the baseline the bucketed layout is measured against.
+ * Both compute the same values up to the order of the FP32 sums inside one
+ * user's projection.
+ */
+typedef enum { DL_LAYOUT_BUCKETED = 0, DL_LAYOUT_WAVEFRONT = 1 } dl_layout;
+
 typedef struct {
   int64_t n_users;          /* I >= 0 */
   int32_t n_items;          /* J >= 1 */
@@ -80,6 +91,7 @@ typedef struct {
   double radius;            /* z (simplex) or u (box), > 0 */
   int32_t jacobi;           /* 1: Jacobi row scaling in the solver (Appendix C) */
   int32_t wg_per_cu;        /* gradient-pass workgroups per compute unit, 0 = default (4) */
+  int32_t layout;           /* dl_layout: user-to-lane mapping of the gradient pass */
   void* stream;             /* hipStream_t */
 } dl_problem_desc;
 

@@ -238,8 +238,11 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   P->mf = (m == 1) ? 1 : 4;
   P->kmax = (m == 1 && !P->has_a) ? DL_KMAX_PLAIN : DL_KMAX_A;
   const int kmax = P->kmax;
+  DL_CHECK_ARG(d->layout == DL_LAYOUT_BUCKETED || d->layout == DL_LAYOUT_WAVEFRONT, "unknown layout");
+  const bool wavefront = d->layout == DL_LAYOUT_WAVEFRONT;
   auto code_of = [&](int64_t dg) -> int {
     if (dg > 64 * (int64_t)kmax) return DL_LONG;
+    if (wavefront) return 6;
     for (int gl = 0; gl <= 6; ++gl)
       if (((dg + (1 << gl) - 1) >> gl) <= kmax) return gl;
     return DL_LONG;

@@ -66,11 +66,14 @@ def _row_vmax(inst, lam32, gamma):
     return np.maximum.reduceat(v, inst.row_ptr[:-1]), v
 
 
+@pytest.mark.parametrize("layout", ["bucketed", "wavefront"])
 @pytest.mark.parametrize("name", CASE_NAMES)
-def test_dual_grad_matches_oracle(dl, orc, cases, name):
+def test_dual_grad_matches_oracle(dl, orc, cases, name, layout):
     import torch
     inst, gamma = cases[name]
-    prob = dl.Problem.from_instance(inst, jacobi=True)
+    prob = dl.Problem.from_instance(inst, jacobi=True, layout=layout)
+    if layout == "wavefront":
+        assert all(g in (6, 7) for g in prob.info()["bucket_glog"][:prob.info()["n_buckets"]])
     lam = _lam_point(orc, inst, gamma, 1)
     lam32 = lam.astype(np.float32).astype(np.float64)
     g, grad, x = prob.dual_grad(torch.from_numpy(lam), gamma, want_obj=True, want_x=True)
