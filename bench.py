@@ -37,6 +37,10 @@ def make_instance(args):
         inst = workloads.production(n_users=args.users, n_items=args.items)
         desc = (f"production {args.users} users x {args.items} items, degree lognormal(4.2,0.6) clipped "
                 f"[1,2000], Zipf(1.1) items, a=1, b=0.3 n_j, simplex<=1")
+    elif args.workload == "appendix_a":
+        inst = workloads.appendix_a(seed=0, n_users=args.users, n_items=args.items, nu=args.nu)
+        desc = (f"appendix-A construction {args.users} users x {args.items} items, nu={args.nu}, lognormal "
+                f"breadth/value/scale, a = s_j c_ij stored, greedy-load b, simplex<=1")
     else:
         inst = workloads.tiny_plain(seed=0, binding=True)
         desc = "tiny_plain 10k users x 100 items, binding capacities"
@@ -88,6 +92,26 @@ def cpu_baseline(inst, budget_s: float):
     return {"value": rate, "unit": "nnz*iter/s", "cores": threads, "kind": "oracle",
             "sample": f"first {S} users ({sample.nnz} nnz) of the same instance, b scaled by {S}/{inst.n_users}, "
                       f"{iters} FP64 iterations in {el:.1f}s"}
+
+
+def six_stage(prob, iters):
+    """The six-stage schedule gamma = 1e3, 1e2, 10, 1, 0.1, 0.01 (the paper's
+    solution-quality runs), each stage warm-started with momentum reset; the
+    certificate (primal, dual, relative gap, max slack) after every stage."""
+    import torch
+    s = prob.solver()
+    rows = []
+    t0 = time.perf_counter()
+    for g in (1e3, 1e2, 1e1, 1e0, 1e-1, 1e-2):
+        s.set_stage(g, 1.0, True)
+        s.step(iters)
+        c = s.certificate()
+        torch.cuda.synchronize()
+        rows.append({"gamma": g, "iters": iters, "primal": c["primal_obj"], "dual": c["dual_obj"],
+                     "rel_gap": c["rel_gap"], "max_slack": c["max_slack"], "elapsed_s": time.perf_counter() - t0})
+        log(f"six-stage gamma {g:g}: primal {c['primal_obj']:.6e} dual {c['dual_obj']:.6e} "
+            f"gap {c['rel_gap']:.3e} slack {c['max_slack']:.3e}")
+    return rows
 
 
 def learned_eval(args, log=log):
@@ -199,7 +223,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="production", choices=["production", "tiny", "batch"])
+    ap.add_argument("--workload", default="production", choices=["production", "tiny", "batch", "appendix_a"])
+    ap.add_argument("--nu", type=float, default=80.0, help="mean nonzeros per user of the appendix-A workload")
+    ap.add_argument("--six-stage", type=int, default=0,
+                    help="also run the six-stage gamma schedule 1e3..1e-2 with this many iterations per stage")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--users", type=int, default=10_000_000)
@@ -315,7 +342,9 @@ def main():
         out["cold_solve_production"] = {"cold_s": time.perf_counter() - t0, "iters": st["iters"], "rel_gap": st["rel_gap"],
                               "status": st["status"], "schedule": "gamma 1e-1,1e-2 (300 each) then 1e-3 to 1e-4 gap"}
         log(f"cold solve: {out['cold_solve_production']}")
-    if args.learned and os.path.exists(args.learned):
+    if args.six_stage:
+        out["six_stage"] = six_stage(prob, args.six_stage)
+    if args.learned and os.path.exists(args.learned) and args.workload == "production":
         del prob
         torch.cuda.empty_cache()
         out["time_to_gap"] = learned_eval(args)

@@ -28,7 +28,7 @@ struct bupd {
   int n_slot;
   int mJ, J;
   int pad;
-  double inv_q[DL_MAX_FAMILIES];
+  const float* qs;  // the instance's fixed-point scales of the pass (device)
   const double* D;
   const double* b;
   double* lam;
@@ -55,7 +55,7 @@ __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict_
   if (r >= u.mJ) return;
   long long acc = 0;
   for (int w = 0; w < u.n_slot; ++w) acc += (long long)u.part[(size_t)w * u.mJ + r];
-  const double ax = (double)acc * u.inv_q[r / u.J];
+  const double ax = (double)acc / (double)u.qs[r / u.J];
   const double Dr = u.D[r];
   const double eta = step_scale * gamma / u.lhat;
   const double gs = Dr * (ax - u.b[r]);
@@ -181,7 +181,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     u.n_slot = w[q];
     u.mJ = P->m * P->J;
     u.J = P->J;
-    for (int k = 0; k < DL_MAX_FAMILIES; ++k) u.inv_q[k] = P->qscale[k] > 0.f ? 1.0 / (double)P->qscale[k] : 0.0;
+    u.qs = P->qs_dev;
     u.D = P->D;
     u.b = P->b;
     u.lam = lam;
@@ -297,6 +297,8 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
     double tk = 1.0;
     int64_t k = 0;
     while ((n_it < 0 || k < n_it) && total < o->max_iters && !live.empty()) {
+      rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
+      if (rc != DL_OK) break;
       rc = dl_launch_grad_batch(B->probs[live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream);
       if (rc != DL_OK) break;
       const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));

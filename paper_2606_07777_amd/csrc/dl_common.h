@@ -93,7 +93,9 @@ struct dl_grad_args {
   int64_t astride;         // elements between stored a families (nnz + DL_PAD)
   int32_t J, m;
   int32_t a_slot[DL_MAX_FAMILIES];  // stored slot of family k, -1: a == 1
-  float qscale[DL_MAX_FAMILIES];    // fixed-point scale of family k
+  float qscale[DL_MAX_FAMILIES];    // coarsest fixed-point scale of family k (max|a_k| * radius)
+  const float* qs_dev;              // m, device: this pass's scales (>= qscale), or NULL
+  const unsigned* ext;              // per-item extremes, encoded: [cneg J][amax, aneg per stored slot, J each]
   // tasks
   const int64_t* wg_task;           // n_wg + 1
   int32_t n_buckets;
@@ -135,6 +137,10 @@ struct dl_problem {
   int a_slot[DL_MAX_FAMILIES] = {-1, -1, -1, -1};
   float qscale[DL_MAX_FAMILIES] = {0, 0, 0, 0};
   int32_t max_degree = 0;
+  // per-item extremes of the stored values (order-preserving uint encoding):
+  // [max(0, -c) over the item's users], then per stored slot [max a], [max -a]
+  unsigned* ext = nullptr;
+  float* qs_dev = nullptr;   // DL_MAX_FAMILIES fixed-point scales of the last histogram pass
 
   // reordered device layout
   int64_t* rp = nullptr;
@@ -184,6 +190,26 @@ dl_status dl_set_partition(dl_problem* P, const std::vector<int64_t>& bounds);
 dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
                                size_t lds, hipStream_t st);
 dl_status dl_grad_prepare(const dl_problem* P);
+// Fixed-point scales for a histogram pass at gather point mu (into P->qs_dev),
+// and the same for every instance of a batched pass (one block per entry).
+dl_status dl_launch_qscale(const dl_problem* P, const float* mu, double gamma);
+dl_status dl_launch_qscale_batch(const dl_grad_args* d_args, int n, hipStream_t st);
+// (Re)computes P->ext from the stored layout; c_only: only the c column.
+dl_status dl_item_extremes(dl_problem* P, bool c_only);
+
+// Order-preserving encoding of floats as unsigned (max of codes = code of max).
+__host__ __device__ inline unsigned dl_ord_enc(float f) {
+  unsigned u;
+  __builtin_memcpy(&u, &f, 4);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float dl_ord_dec(unsigned e) {
+  unsigned u = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+constexpr unsigned DL_ORD_NEG_INF = 0x007FFFFFu;  // dl_ord_enc(-inf)
 
 // BF16 helpers (storage form: c and a in bfloat16, FP32 arithmetic).
 __host__ __device__ inline uint16_t dl_f32_to_bf16_rne(float f) {

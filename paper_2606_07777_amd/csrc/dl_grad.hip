@@ -245,7 +245,8 @@ template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
                                              RowRegs<MF, HAS_A, KMAX>& R, const float* s_rf,
                                              unsigned long long* s_hist, double& acc,
-                                             const float (&cc)[(MODE & M_REPAIR) ? KMAX : 1]) {
+                                             const float (&cc)[(MODE & M_REPAIR) ? KMAX : 1],
+                                             const float (&qs)[DL_MAX_FAMILIES]) {
   constexpr int G = 1 << GLOG;
   K = __builtin_amdgcn_readfirstlane(K);
   float (&v)[KMAX] = R.c;
@@ -316,8 +317,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
             if constexpr (HAS_A) {
               if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
             }
-            if constexpr (HAS_A) hist_add(s_hist, f * A.J + R.j[k], w, A.qscale[f]);
-            else hist_add_pos(s_hist, f * A.J + R.j[k], w, A.qscale[f]);
+            if constexpr (HAS_A) hist_add(s_hist, f * A.J + R.j[k], w, qs[f]);
+            else hist_add_pos(s_hist, f * A.J + R.j[k], w, qs[f]);
           }
         }
       }
@@ -346,7 +347,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
 template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucket& B, int64_t t0, int64_t t1,
                                            int lane, const float* s_mu, const float* s_rf,
-                                           unsigned long long* s_hist, double& acc) {
+                                           unsigned long long* s_hist, double& acc,
+                                           const float (&qs)[DL_MAX_FAMILIES]) {
   if (t0 >= t1) return;
   // keeps per-bucket lane arithmetic inside this bucket's code (otherwise it is
   // hoisted out of the kernel's bucket loop for every bucket at once and spills)
@@ -368,7 +370,7 @@ __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucke
       const int K = kof(m);
       load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R);
       gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R, s_mu, cc);
-      project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R, s_rf, s_hist, acc, cc);
+      project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R, s_rf, s_hist, acc, cc, qs);
     }
     return;
   }
@@ -387,7 +389,7 @@ __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucke
       load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB);
       if (t + 2 * DL_WAVES < t1) mc = load_meta<GLOG>(A, B, t + 2 * DL_WAVES, lane, need_os);
     }
-    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA, s_rf, s_hist, acc, cc);
+    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA, s_rf, s_hist, acc, cc, qs);
     t += DL_WAVES;
     if (t >= t1) break;
     gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB, s_mu, cc);
@@ -397,7 +399,7 @@ __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucke
       load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mc, ka, lid, RA);
       if (t + 2 * DL_WAVES < t1) md = load_meta<GLOG>(A, B, t + 2 * DL_WAVES, lane, need_os);
     }
-    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB, s_rf, s_hist, acc, cc);
+    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB, s_rf, s_hist, acc, cc, qs);
     t += DL_WAVES;
     if (t >= t1) break;
     ma = mc;
@@ -431,7 +433,8 @@ __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu
 
 template <int MF, bool HAS_A, typename TV, int MODE>
 __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, const dl_bucket& B, const float* s_mu,
-                                          const float* s_rf, unsigned long long* s_hist, int lane, double& acc) {
+                                          const float* s_rf, unsigned long long* s_hist, int lane, double& acc,
+                                          const float (&qs)[DL_MAX_FAMILIES]) {
   const int64_t u = B.user_begin + (t - B.task_begin);
   const int64_t s = A.rp[u];
   const int d = (int)(A.rp[u + 1] - s);
@@ -486,8 +489,8 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
       for (int f = 0; f < MF; ++f) {
         if (f < A.m) {
           float w = (HAS_A && A.a_slot[f] >= 0) ? af[HAS_A ? f : 0] * x : x;
-          if constexpr (HAS_A) hist_add(s_hist, f * A.J + j, w, A.qscale[f]);
-          else hist_add_pos(s_hist, f * A.J + j, w, A.qscale[f]);
+          if constexpr (HAS_A) hist_add(s_hist, f * A.J + j, w, qs[f]);
+          else hist_add_pos(s_hist, f * A.J + j, w, qs[f]);
         }
       }
     }
@@ -527,6 +530,11 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
   const int wave = tid >> 6;
   const int lane = tid & 63;
   double acc = 0.0;
+  // this pass's fixed-point scales (uniform)
+  float qs[DL_MAX_FAMILIES];
+#pragma unroll
+  for (int f = 0; f < DL_MAX_FAMILIES; ++f)
+    qs[f] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.qs_dev ? A.qs_dev[f] : A.qscale[f])));
   for (int b = 0; b < A.n_buckets; ++b) {
     const dl_bucket& B = A.bk[b];
     const int64_t b1 = (b + 1 < A.n_buckets) ? A.bk[b + 1].task_begin : w1;
@@ -537,16 +545,16 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
     int64_t first = w0 + wave;
     if (first < lo) first += ((lo - first + DL_WAVES - 1) / DL_WAVES) * DL_WAVES;
     switch (B.glog) {
-      case 0: run_bucket<0, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
-      case 1: run_bucket<1, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
-      case 2: run_bucket<2, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
-      case 3: run_bucket<3, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
-      case 4: run_bucket<4, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
-      case 5: run_bucket<5, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
-      case 6: run_bucket<6, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc); break;
+      case 0: run_bucket<0, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
+      case 1: run_bucket<1, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
+      case 2: run_bucket<2, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
+      case 3: run_bucket<3, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
+      case 4: run_bucket<4, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
+      case 5: run_bucket<5, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
+      case 6: run_bucket<6, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
       default:
         for (int64_t t = first; t < hi; t += DL_WAVES)
-          long_task<MF, HAS_A, TV, MODE>(A, t, B, s_mu, s_rf, s_hist, lane, acc);
+          long_task<MF, HAS_A, TV, MODE>(A, t, B, s_mu, s_rf, s_hist, lane, acc, qs);
         break;
     }
   }
@@ -640,7 +648,78 @@ void set_attr_all() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
+// Fixed-point scale of each family for one histogram pass.  For every item j
+// and user i, exactly (a >= 0 or not, lam of any sign):
+//   v_ij = -(c_ij + sum_k a_kij mu_kj) / gamma
+//        <= (max_i(-c_ij)^+ + sum_k max(-amin_kj mu_kj, -amax_kj mu_kj)) / gamma,
+// x_ij <= min(z, max(0, v_ij)) (box, simplex <=; theta >= 0) or x_ij <= z
+// (simplex =), so |a_kij x_ij| <= B_k = max_j max|a_kj| xmax_j.  The scale
+// 2^(30 - ceil(log2 B_k)) keeps every fixed-point addend below 2^30 (FP32
+// rounding of v stays far inside the factor-2 headroom of int32) and makes
+// the grid as fine as the pass allows; it never drops below the coarsest
+// scale (max|a_k| * radius).  One block of 1024 lanes; deterministic.
+__device__ void qscale_body(const dl_grad_args& A, float* out) {
+  __shared__ float sh[1024];
+  const int J = A.J, m = A.m;
+  const double inv_gamma = -(double)A.neg_inv_gamma;
+  float bk[DL_MAX_FAMILIES] = {0.f, 0.f, 0.f, 0.f};
+  for (int j = threadIdx.x; j < J; j += blockDim.x) {
+    const unsigned ec = A.ext[j];
+    if (ec == DL_ORD_NEG_INF) continue;  // no user is eligible for item j
+    double t = (double)dl_ord_dec(ec);
+    float amx[DL_MAX_FAMILIES], ang[DL_MAX_FAMILIES];
+    for (int k = 0; k < m; ++k) {
+      const int sl = A.a_slot[k];
+      amx[k] = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(1 + 2 * sl) * J + j]) : 1.f;
+      ang[k] = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(2 + 2 * sl) * J + j]) : -1.f;
+      const double mu = (double)A.mu[(size_t)k * J + j];
+      t += mu >= 0.0 ? (double)ang[k] * mu : (double)amx[k] * (-mu);
+    }
+    const double v = t * inv_gamma;
+    const double z = (double)A.radius;
+    const double xm = (A.proj == DL_PROJ_SIMPLEX_EQ) ? z : fmin(z, fmax(0.0, v));
+    for (int k = 0; k < m; ++k) bk[k] = fmaxf(bk[k], (float)(fmax(fabs((double)amx[k]), fabs((double)ang[k])) * xm));
+  }
+  for (int k = 0; k < m; ++k) {
+    sh[threadIdx.x] = bk[k];
+    __syncthreads();
+    for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+      if ((int)threadIdx.x < s2) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s2]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const float B = sh[0] * (1.0f + 0x1p-20f);  // rounding of the bound itself
+      float q = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
+      q = fminf(fmaxf(q, A.qscale[k]), 0x1p60f);
+      out[k] = q;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(1024) qscale_kernel(dl_grad_args A, float* out) { qscale_body(A, out); }
+
+__global__ void __launch_bounds__(1024) qscale_batch_kernel(const dl_grad_args* __restrict__ args) {
+  const dl_grad_args& A = args[blockIdx.x];
+  if (A.qs_dev == nullptr || A.ext == nullptr) return;  // not a live instance
+  qscale_body(A, const_cast<float*>(A.qs_dev));
+}
+
 }  // namespace
+
+dl_status dl_launch_qscale(const dl_problem* P, const float* mu, double gamma) {
+  dl_grad_args A = dl_make_grad_args(P, mu, gamma);
+  hipLaunchKernelGGL(qscale_kernel, dim3(1), dim3(1024), 0, P->stream, A, P->qs_dev);
+  DL_HIP_TRY(hipGetLastError());
+  return DL_OK;
+}
+
+dl_status dl_launch_qscale_batch(const dl_grad_args* d_args, int n, hipStream_t st) {
+  if (n <= 0) return DL_OK;
+  hipLaunchKernelGGL(qscale_batch_kernel, dim3(n), dim3(1024), 0, st, d_args);
+  DL_HIP_TRY(hipGetLastError());
+  return DL_OK;
+}
 
 size_t dl_grad_lds_bytes(const dl_problem* P, int mode) {
   const size_t mJ = (size_t)P->m * P->J;
@@ -703,6 +782,8 @@ dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamm
   A.neg_inv_gamma = (float)(-1.0 / gamma);
   A.gamma = (float)gamma;
   A.mu = mu;
+  A.qs_dev = P->qs_dev;
+  A.ext = P->ext;
   A.part = P->part;
   A.wg_clock = P->clocking ? P->wg_clock : nullptr;
   return A;
@@ -712,6 +793,7 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
                          const float* v_in, float* x_out, double* obj_part) {
   if (P->n_wg <= 0) return DL_OK;
   if (x_out) mode |= M_XOUT;
+  if (mode & M_HIST) DL_TRY(dl_launch_qscale(P, mu, gamma));
   dl_grad_args A = dl_make_grad_args(P, mu, gamma);
   A.rfac = rfac;
   A.v_in = v_in;

@@ -126,6 +126,30 @@ __global__ void regather_c(const int64_t* orig_rp, const int64_t* new_rp, int64_
   if (bad) atomicOr(flag, 1);
 }
 
+// Per-item maximum of one stored quantity (kind 0: max(0, -c); 1: a; 2: -a)
+// in the order-preserving encoding: block-local LDS maxima, then one global
+// atomic maximum per item and block.
+template <typename TV>
+__global__ void item_extreme(const int32_t* __restrict__ idx, const TV* __restrict__ val, int64_t nnz, int J,
+                             int kind, unsigned* __restrict__ out) {
+  extern __shared__ unsigned s_ext[];
+  for (int j = threadIdx.x; j < J; j += blockDim.x) s_ext[j] = DL_ORD_NEG_INF;
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    float v = ld<TV>(val, e);
+    float q = kind == 0 ? fmaxf(0.f, -v) : (kind == 1 ? v : -v);
+    atomicMax(&s_ext[idx[e]], dl_ord_enc(q));
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < J; j += blockDim.x)
+    if (s_ext[j] != DL_ORD_NEG_INF) atomicMax(&out[j], s_ext[j]);
+}
+
+__global__ void fill_u32(unsigned* p, int64_t n, unsigned v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 template <typename T>
 dl_status dmalloc(dl_problem* P, T** p, size_t n) {
   *p = nullptr;
@@ -138,7 +162,7 @@ dl_status dmalloc(dl_problem* P, T** p, size_t n) {
 void free_problem(dl_problem* P) {
   if (!P) return;
   void* ptrs[] = {P->rp, P->idx, P->cval, P->aval, P->orig_rp, P->wg_task, P->wg_clock, P->b, P->D, P->part, P->acc,
-                  P->obj_part, P->pobj_part, P->mu, P->rfac, P->lam_tmp, P->cert_out};
+                  P->obj_part, P->pobj_part, P->mu, P->rfac, P->lam_tmp, P->cert_out, P->ext, P->qs_dev};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->cert_host) (void)hipHostFree(P->cert_host);
@@ -414,6 +438,10 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   DL_TRY(dmalloc(P, &P->lam_tmp, (size_t)mJ));
   DL_TRY(dmalloc(P, &P->cert_out, 16));
   DL_HIP_TRY(hipHostMalloc((void**)&P->cert_host, sizeof(double) * 16, hipHostMallocDefault));
+  DL_TRY(dmalloc(P, &P->qs_dev, (size_t)DL_MAX_FAMILIES));
+  DL_HIP_TRY(hipMemcpyAsync(P->qs_dev, P->qscale, sizeof(float) * DL_MAX_FAMILIES, hipMemcpyHostToDevice, st));
+  DL_TRY(dmalloc(P, &P->ext, (size_t)J * (size_t)(1 + 2 * P->n_stored)));
+  DL_TRY(dl_item_extremes(P, false));
   DL_TRY(dl_grad_prepare(P));
   DL_HIP_TRY(hipStreamSynchronize(st));
   return DL_OK;
@@ -489,6 +517,35 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** ou
   return DL_OK;
 }
 
+dl_status dl_item_extremes(dl_problem* P, bool c_only) {
+  const int J = P->J;
+  const int n_q = c_only ? 1 : 1 + 2 * P->n_stored;
+  hipStream_t st = P->stream;
+  const int64_t tot = (int64_t)J * n_q;
+  hipLaunchKernelGGL(fill_u32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, P->ext, tot, DL_ORD_NEG_INF);
+  DL_HIP_TRY(hipGetLastError());
+  if (P->nnz == 0) return DL_OK;
+  const unsigned blocks = (unsigned)std::min<int64_t>(1024, (P->nnz + 1023) / 1024);
+  const size_t lds = sizeof(unsigned) * (size_t)J;
+  const bool bf16 = P->storage == DL_BF16;
+  for (int q = 0; q < n_q; ++q) {
+    const int kind = q == 0 ? 0 : (q % 2 == 1 ? 1 : 2);
+    const int slot = q == 0 ? 0 : (q - 1) / 2;
+    const void* val = q == 0 ? P->cval
+                             : (const void*)((const char*)P->aval + (size_t)slot * (size_t)(P->nnz + DL_PAD) *
+                                                                       (bf16 ? 2 : 4));
+    unsigned* out = P->ext + (size_t)q * J;
+    if (bf16)
+      hipLaunchKernelGGL(item_extreme<uint16_t>, dim3(blocks), dim3(1024), lds, st, P->idx,
+                         (const uint16_t*)val, P->nnz, J, kind, out);
+    else
+      hipLaunchKernelGGL(item_extreme<float>, dim3(blocks), dim3(1024), lds, st, P->idx, (const float*)val, P->nnz,
+                         J, kind, out);
+    DL_HIP_TRY(hipGetLastError());
+  }
+  return DL_OK;
+}
+
 extern "C" void dl_problem_destroy(dl_problem* P) { free_problem(P); }
 
 extern "C" dl_status dl_problem_update(dl_problem* P, const float* c, const double* b) {
@@ -508,6 +565,7 @@ extern "C" dl_status dl_problem_update(dl_problem* P, const float* c, const doub
     DL_HIP_TRY(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     DL_HIP_TRY(hipStreamSynchronize(st));
     DL_CHECK_ARG(!hf, "c has a non-finite entry (the problem's c is now partly updated)");
+    DL_TRY(dl_item_extremes(P, true));
   }
   if (b) {
     P->b_host.assign(b, b + mJ);

@@ -18,7 +18,7 @@ struct upd_args {
   unsigned long long* acc;  // reduced per-item sums (read and cleared)
   int n_wg;
   int mJ, J;
-  double inv_q[DL_MAX_FAMILIES];
+  const float* qs;  // fixed-point scale of each family in the pass being reduced (device)
   const double* D;
   const double* b;
   double* lam;      // scaled lam'
@@ -61,7 +61,7 @@ __global__ void update_kernel(upd_args U) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= U.mJ) return;
   const int k = r / U.J;
-  const double ax = take_sum(U.acc, r) * U.inv_q[k];
+  const double ax = take_sum(U.acc, r) / (double)U.qs[k];
   const double Dr = U.D[r];
   const double gs = Dr * (ax - U.b[r]);
   const double lo = U.lam[r];
@@ -79,7 +79,7 @@ __global__ void reduce_kernel(upd_args U) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= U.mJ) return;
   const int k = r / U.J;
-  const double ax = take_sum(U.acc, r) * U.inv_q[k];
+  const double ax = take_sum(U.acc, r) / (double)U.qs[k];
   if (U.ax_out) U.ax_out[r] = ax;
   if (U.grad_out) U.grad_out[r] = ax - U.b[r];
 }
@@ -223,7 +223,7 @@ upd_args make_upd(const dl_problem* P) {
   U.n_wg = P->n_wg;
   U.mJ = P->m * P->J;
   U.J = P->J;
-  for (int k = 0; k < DL_MAX_FAMILIES; ++k) U.inv_q[k] = P->qscale[k] > 0.f ? 1.0 / (double)P->qscale[k] : 0.0;
+  U.qs = P->qs_dev;
   U.D = P->D;
   U.b = P->b;
   return U;

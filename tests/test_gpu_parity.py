@@ -36,11 +36,12 @@ def _cases(wl):
         "simplex_eq": (wl.random_small(53, 4000, 200, 150, proj="simplex_eq"), 1e-2),
         "explicit_a": (wl.random_small(54, 4000, 500, 300, a_ones=False), 1e-2),
         "production_small": (wl.production(n_users=100_000, n_items=10_000), 1e-2),
+        "appendix_a": (wl.appendix_a(seed=3, n_users=20_000, n_items=300, nu=12.0), 1.0),
     }
 
 
 CASE_NAMES = ["tiny_plain_binding", "all_buckets_long_rows", "two_family_box", "simplex_eq", "explicit_a",
-              "production_small"]
+              "production_small", "appendix_a"]
 
 
 @pytest.fixture(scope="module")
@@ -157,6 +158,31 @@ def test_continuation_solve_matches_oracle(dl, orc, wl):
     # both certified to 1e-4: their dual values agree to the certified tolerance
     assert abs(st["dual_obj"] - so["dual_obj"]) <= 2e-4 * abs(so["dual_obj"])
     print(f"gpu iters {st['iters']} gap {st['rel_gap']:.2e}; oracle iters {so['iters']} gap {so['rel_gap']:.2e}")
+
+
+def test_appendix_a_six_stage_schedule(dl, orc, wl):
+    """The paper's six-stage schedule (gamma 1e3 ... 1e-2, Table 4) on the
+    Appendix-A construction, shortened to 100 iterations per stage: lam after
+    every stage against the FP64 oracle, from the same warm starts."""
+    import torch
+    inst = wl.appendix_a(seed=4, n_users=20_000, n_items=300, nu=12.0)
+    gammas = [1e3, 1e2, 1e1, 1e0, 1e-1, 1e-2]
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    s = prob.solver()
+    lam_o = None
+    for g in gammas:
+        s.set_stage(g, 1.0, True)
+        s.step(100)
+        lo, so, _, _ = orc.solve(inst, [g], [100], jacobi=True, check_every=0, lam0=lam_o)
+        lg = s.lam().cpu().numpy()
+        rel = np.linalg.norm(lg - lo) / max(np.linalg.norm(lo), 1e-300)
+        print(f"gamma {g:g}: |lam| {np.linalg.norm(lo):.3e} rel err {rel:.2e}")
+        assert rel <= 1e-5, (g, rel)
+        # continue both from the oracle's point so stage errors do not compound
+        lam_o = lo
+        s = prob.solver(torch.from_numpy(lo))
+    cert = s.certificate()
+    print(f"certificate after the schedule: {cert}")
 
 
 def test_bitwise_deterministic(dl, cases):

@@ -86,3 +86,46 @@ def test_oracle_and_library_are_independent():
                     code = "\n".join(l for l in txt.splitlines()
                                      if l.strip().startswith(("import", "from", "#include")))
                     assert not re.search(banned, code), os.path.join(dp, f)
+
+
+def test_appendix_a_construction(wl):
+    """The Appendix-A recipe, checked against its own definition: per-item counts,
+    a = s_j * value with one scale per item, the value cap, and capacities
+    b = rho (greedy load + eps) with rho in [0.5, 1] and the greedy load
+    recomputed here from the rows."""
+    inst = wl.appendix_a(seed=7, n_users=20_000, n_items=300, nu=12.0, c_max=6.0, eps0=1e-3)
+    assert inst.n_families == 1 and inst.a.shape == (1, inst.nnz)
+    assert np.array_equal(inst.item_counts(), inst.meta["item_counts"])
+    assert abs(inst.nnz / inst.n_users - 12.0) < 0.5
+    for i in range(0, inst.n_users, 97):
+        row = inst.item_idx[inst.row_ptr[i]:inst.row_ptr[i + 1]]
+        assert np.all(np.diff(row) > 0)
+    val = -inst.c.astype(np.float64)
+    assert np.all(val > 0) and val.max() <= 6.0 and np.any(val == np.float32(6.0))
+    ratio = inst.a[0].astype(np.float64) / val
+    for j in range(0, 300, 7):
+        r = ratio[inst.item_idx == j]
+        if r.size:
+            assert np.allclose(r, r[0], rtol=1e-6), j
+    load = np.zeros(300)
+    a = inst.a[0]
+    for i in range(inst.n_users):
+        s, e = inst.row_ptr[i], inst.row_ptr[i + 1]
+        if e > s:
+            k = s + int(np.argmax(a[s:e]))
+            load[inst.item_idx[k]] += float(a[k])
+    rho = inst.b[0] / (load + 1e-3)
+    assert np.all(rho >= 0.5 - 1e-12) and np.all(rho <= 1.0 + 1e-12)
+    assert rho.std() > 0.1  # drawn, not constant
+
+
+def test_appendix_a_thread_count_independent(wl):
+    code = ("import workloads as w, hashlib; p = w.appendix_a(seed=1, n_users=30000, n_items=500); "
+            "print(hashlib.sha1(p.row_ptr.tobytes() + p.item_idx.tobytes() + p.c.tobytes() + p.a.tobytes()"
+            " + p.b.tobytes()).hexdigest())")
+    outs = set()
+    for t in ("1", "4"):
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                           env=dict(os.environ, OMP_NUM_THREADS=t), check=True)
+        outs.add(r.stdout.strip())
+    assert len(outs) == 1

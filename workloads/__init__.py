@@ -65,6 +65,23 @@ class _Params(ctypes.Structure):
     ]
 
 
+class _AppxParams(ctypes.Structure):
+    _fields_ = [
+        ("n_users", ctypes.c_int64),
+        ("n_items", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("nu", ctypes.c_double),
+        ("breadth_sigma", ctypes.c_double),
+        ("value_sigma", ctypes.c_double),
+        ("resp_sigma", ctypes.c_double),
+        ("noise_sigma", ctypes.c_double),
+        ("c_max", ctypes.c_double),
+        ("scale_sigma", ctypes.c_double),
+        ("eps0", ctypes.c_double),
+    ]
+
+
 def build(force: bool = False) -> str:
     """Compiles the generator into a shared library next to its source."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -88,6 +105,10 @@ def _load():
         lib.wl_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
                                 ctypes.c_int, ctypes.c_void_p]
         lib.wl_draw.restype = ctypes.c_int
+        lib.wl_appx_counts.argtypes = [ctypes.POINTER(_AppxParams), ctypes.c_void_p]
+        lib.wl_appx_counts.restype = ctypes.c_int64
+        lib.wl_appx_fill.argtypes = [ctypes.POINTER(_AppxParams)] + [ctypes.c_void_p] * 6
+        lib.wl_appx_fill.restype = ctypes.c_int
         lib.wl_philox4x32_10.argtypes = [ctypes.c_void_p] * 3
         lib.wl_philox4x32_10.restype = None
         _lib = lib
@@ -241,6 +262,37 @@ def batch_member(k: int, binding: bool = True, scale: float = 1.0) -> Instance:
     b = np.full((1, J), float(level), dtype=np.float64)
     return Instance(f"batch_member{k}", I, J, 1, rp, idx, c, None, b, "simplex_le", 1.0,
                     {"seed": seed, "binding": binding})
+
+
+def appendix_a(seed: int = 0, n_users: int = 100_000, n_items: int = 1000, nu: float = 20.0,
+               breadth_sigma: float = 1.0, value_sigma: float = 0.5, resp_sigma: float = 0.5,
+               noise_sigma: float = 0.25, c_max: float = 10.0, scale_sigma: float = 1.0,
+               eps0: float = 1e-3) -> Instance:
+    """The paper's Appendix-A construction (resource-major, greedy-load capacities).
+
+    Users are the paper's requests, items its resources.  The solver minimises,
+    so c = -value; a = s_j * value; per-user simplex sum x <= 1.  The
+    distribution parameters (which the paper does not publish) are arguments.
+    """
+    p = _AppxParams()
+    p.n_users, p.n_items, p.seed = int(n_users), int(n_items), int(seed)
+    p.nu, p.breadth_sigma, p.value_sigma, p.resp_sigma = float(nu), float(breadth_sigma), float(value_sigma), \
+        float(resp_sigma)
+    p.noise_sigma, p.c_max, p.scale_sigma, p.eps0 = float(noise_sigma), float(c_max), float(scale_sigma), float(eps0)
+    lib = _load()
+    K = np.empty(int(n_items), dtype=np.int64)
+    nnz = lib.wl_appx_counts(ctypes.byref(p), K.ctypes.data)
+    assert nnz >= 0, f"wl_appx_counts failed ({nnz})"
+    rp = np.empty(int(n_users) + 1, dtype=np.int64)
+    idx = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float32)
+    a = np.empty((1, nnz), dtype=np.float32)
+    b = np.empty((1, int(n_items)), dtype=np.float64)
+    rc = lib.wl_appx_fill(ctypes.byref(p), K.ctypes.data, rp.ctypes.data, idx.ctypes.data, val.ctypes.data,
+                          a.ctypes.data, b.ctypes.data)
+    assert rc == 0, f"wl_appx_fill failed ({rc})"
+    return Instance("appendix_a", int(n_users), int(n_items), 1, rp, idx, -val, a, b, "simplex_le", 1.0,
+                    {"seed": seed, "nu": nu, "item_counts": K})
 
 
 def cadence_base(chain: int, n_users: int = 1_000_000, n_items: int = 5000) -> Instance:

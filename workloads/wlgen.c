@@ -344,6 +344,202 @@ int wl_fill(const wl_params* p, const int64_t* row_ptr, int32_t* item_idx, float
   return failed ? -3 : 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The paper's Appendix-A construction                                       */
+/* ------------------------------------------------------------------------ */
+/* Resource-major generation (Appendix A): every resource (item) j draws a
+ * lognormal breadth, its share p_j of the total breadth sets the number of
+ * incident requests (users) K_j ~ Poisson(p_j I nu) truncated at I, and it
+ * picks K_j distinct users.  Edge value c_ij = min(v_j u_i eps_ij, c_max)
+ * (v, u, eps lognormal), coefficient a_ij = s_j c_ij (s lognormal), capacity
+ * b_j = rho_j (l_j + eps0) with l_j the greedy load (each user gives its
+ * largest a_ij to that resource) and rho_j ~ U[0.5, 1].  The paper leaves the
+ * distribution parameters open; they are arguments here. */
+typedef struct {
+  int64_t n_users;
+  int32_t n_items;
+  int32_t pad0;
+  uint64_t seed;
+  double nu;            /* mean nonzeros per user */
+  double breadth_sigma; /* log-sd of the resource breadth */
+  double value_sigma;   /* log-sd of v_j */
+  double resp_sigma;    /* log-sd of u_i */
+  double noise_sigma;   /* log-sd of eps_ij */
+  double c_max;         /* cap of the edge value */
+  double scale_sigma;   /* log-sd of s_j */
+  double eps0;          /* added to the greedy load */
+} wl_appx_params;
+
+#define S_APPX_BREADTH 40u
+#define S_APPX_COUNT 41u
+#define S_APPX_PICK 42u
+#define S_APPX_VJ 43u
+#define S_APPX_UI 44u
+#define S_APPX_EDGE 45u
+#define S_APPX_SJ 46u
+#define S_APPX_RHO 47u
+
+/* Poisson count: inversion for small means, else the normal approximation
+ * round(mean + sqrt(mean) N(0,1)) clipped at 0. */
+static int64_t appx_poisson(rng_t* r, double mean) {
+  if (mean < 100.0) return rng_poisson(r, mean);
+  double x = mean + sqrt(mean) * rng_normal(r);
+  return x < 0.0 ? 0 : (int64_t)llround(x);
+}
+
+/* K[j] for every resource; returns the number of edges (or < 0). */
+int64_t wl_appx_counts(const wl_appx_params* p, int64_t* K) {
+  if (!p || !K || p->n_users <= 0 || p->n_items <= 0) return -1;
+  const int32_t J = p->n_items;
+  double* w = (double*)malloc(sizeof(double) * (size_t)J);
+  if (!w) return -2;
+  double tot = 0.0;
+  for (int32_t j = 0; j < J; ++j) {
+    rng_t r;
+    rng_init(&r, p->seed, S_APPX_BREADTH, (uint64_t)j);
+    w[j] = exp(p->breadth_sigma * rng_normal(&r));
+    tot += w[j];
+  }
+  int64_t nnz = 0;
+  for (int32_t j = 0; j < J; ++j) {
+    rng_t r;
+    rng_init(&r, p->seed, S_APPX_COUNT, (uint64_t)j);
+    int64_t k = appx_poisson(&r, w[j] / tot * (double)p->n_users * p->nu);
+    if (k > p->n_users) k = p->n_users;
+    K[j] = k;
+    nnz += k;
+  }
+  free(w);
+  return nnz;
+}
+
+typedef struct {
+  int32_t item;
+  float c, a;
+} appx_edge;
+
+static int cmp_edge(const void* x, const void* y) {
+  const int32_t a = ((const appx_edge*)x)->item, b = ((const appx_edge*)y)->item;
+  return (a > b) - (a < b);
+}
+
+/* Fills the user-major CSR (rows sorted by item), c (the value, >= 0), a and b. */
+int wl_appx_fill(const wl_appx_params* p, const int64_t* K, int64_t* row_ptr, int32_t* item_idx, float* c,
+                 float* a, double* b) {
+  if (!p || !K || !row_ptr || !item_idx || !c || !a || !b) return -1;
+  const int64_t I = p->n_users;
+  const int32_t J = p->n_items;
+  int64_t* kofs = (int64_t*)malloc(sizeof(int64_t) * ((size_t)J + 1));
+  kofs[0] = 0;
+  for (int32_t j = 0; j < J; ++j) kofs[j + 1] = kofs[j] + K[j];
+  const int64_t nnz = kofs[J];
+  int32_t* user_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  float* cv = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+  double* ui = (double*)malloc(sizeof(double) * (size_t)I);
+  int64_t* deg = (int64_t*)calloc((size_t)I + 1, sizeof(int64_t));
+  double* sj = (double*)malloc(sizeof(double) * (size_t)J);
+  if (!kofs || !user_of || !cv || !ui || !deg || !sj) return -2;
+  if (I > 2147483647LL) return -4;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < I; ++i) {
+    rng_t r;
+    rng_init(&r, p->seed, S_APPX_UI, (uint64_t)i);
+    ui[i] = exp(p->resp_sigma * rng_normal(&r));
+  }
+  for (int32_t j = 0; j < J; ++j) {
+    rng_t r;
+    rng_init(&r, p->seed, S_APPX_SJ, (uint64_t)j);
+    sj[j] = exp(p->scale_sigma * rng_normal(&r));
+  }
+  const size_t words = ((size_t)I + 63) / 64;
+#pragma omp parallel
+  {
+    uint64_t* seen = (uint64_t*)calloc(words, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 1)
+    for (int32_t j = 0; j < J; ++j) {
+      int32_t* lst = user_of + kofs[j];
+      const int64_t k = K[j];
+      rng_t r;
+      rng_init(&r, p->seed, S_APPX_PICK, (uint64_t)j);
+      if (2 * k <= I) {
+        /* distinct users by redrawing repeats */
+        for (int64_t n = 0; n < k;) {
+          int64_t t = (int64_t)(rng_u01(&r) * (double)I);
+          if (t >= I) t = I - 1;
+          if (seen[t >> 6] & (1ull << (t & 63))) continue;
+          seen[t >> 6] |= 1ull << (t & 63);
+          lst[n++] = (int32_t)t;
+        }
+        for (int64_t n = 0; n < k; ++n) seen[lst[n] >> 6] &= ~(1ull << (lst[n] & 63));
+      } else {
+        /* Floyd's sampling for dense resources */
+        int64_t n = 0;
+        for (int64_t jj = I - k; jj < I; ++jj) {
+          int64_t t = (int64_t)(rng_u01(&r) * (double)(jj + 1));
+          if (t > jj) t = jj;
+          if (seen[t >> 6] & (1ull << (t & 63))) t = jj;
+          seen[t >> 6] |= 1ull << (t & 63);
+          lst[n++] = (int32_t)t;
+        }
+        for (int64_t e = 0; e < k; ++e) seen[lst[e] >> 6] &= ~(1ull << (lst[e] & 63));
+      }
+      rng_t rv, re;
+      rng_init(&rv, p->seed, S_APPX_VJ, (uint64_t)j);
+      const double vj = exp(p->value_sigma * rng_normal(&rv));
+      rng_init(&re, p->seed, S_APPX_EDGE, (uint64_t)j);
+      for (int64_t n = 0; n < k; ++n) {
+        double val = vj * ui[lst[n]] * exp(p->noise_sigma * rng_normal(&re));
+        cv[kofs[j] + n] = (float)(val < p->c_max ? val : p->c_max);
+      }
+    }
+    free(seen);
+  }
+  /* user-major transpose: counts, offsets, scatter, then each row sorted by item */
+  for (int64_t e = 0; e < nnz; ++e) deg[user_of[e]]++;
+  row_ptr[0] = 0;
+  for (int64_t i = 0; i < I; ++i) row_ptr[i + 1] = row_ptr[i] + deg[i];
+  appx_edge* ed = (appx_edge*)malloc(sizeof(appx_edge) * (size_t)(nnz > 0 ? nnz : 1));
+  for (int64_t i = 0; i < I; ++i) deg[i] = row_ptr[i];
+  for (int32_t j = 0; j < J; ++j)
+    for (int64_t n = kofs[j]; n < kofs[j + 1]; ++n) {
+      const int32_t u = user_of[n];
+      appx_edge x = {j, cv[n], (float)(sj[j] * (double)cv[n])};
+      ed[deg[u]++] = x;
+    }
+  double* load = (double*)calloc((size_t)J, sizeof(double));
+  int32_t* best_j = (int32_t*)malloc(sizeof(int32_t) * (size_t)I);
+  float* best_a = (float*)malloc(sizeof(float) * (size_t)I);
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < I; ++i) {
+    const int64_t s0 = row_ptr[i], d = row_ptr[i + 1] - s0;
+    if (d > 1) qsort(ed + s0, (size_t)d, sizeof(appx_edge), cmp_edge);
+    int32_t bj = -1;
+    float ba = -1.f;
+    for (int64_t e = 0; e < d; ++e) {
+      item_idx[s0 + e] = ed[s0 + e].item;
+      c[s0 + e] = ed[s0 + e].c;
+      a[s0 + e] = ed[s0 + e].a;
+      if (ed[s0 + e].a > ba) {
+        ba = ed[s0 + e].a;
+        bj = ed[s0 + e].item;
+      }
+    }
+    best_j[i] = bj;
+    best_a[i] = ba;
+  }
+  /* greedy loads, summed in user order */
+  for (int64_t i = 0; i < I; ++i)
+    if (best_j[i] >= 0) load[best_j[i]] += (double)best_a[i];
+  for (int32_t j = 0; j < J; ++j) {
+    rng_t r;
+    rng_init(&r, p->seed, S_APPX_RHO, (uint64_t)j);
+    b[j] = (0.5 + 0.5 * rng_u01(&r)) * (load[j] + p->eps0);
+  }
+  free(kofs); free(user_of); free(cv); free(ui); free(deg); free(sj); free(ed); free(load); free(best_j);
+  free(best_a);
+  return 0;
+}
+
 /* Uniform and normal draws for drift and other per-element perturbations:
  * out[n] for entities [first, first+n) on the given stream. kind 0: U[0,1),
  * kind 1: N(0,1). */
