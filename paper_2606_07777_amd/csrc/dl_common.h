@@ -95,7 +95,7 @@ struct dl_grad_args {
   int32_t a_slot[DL_MAX_FAMILIES];  // stored slot of family k, -1: a == 1
   float qscale[DL_MAX_FAMILIES];    // coarsest fixed-point scale of family k (max|a_k| * radius)
   const float* qs_dev;              // m, device: this pass's scales (>= qscale), or NULL
-  const unsigned* ext;              // per-item extremes, encoded: [cneg J][amax, aneg per stored slot, J each]
+  const unsigned* ext;              // per-item extremes, encoded: [max(0,-c)][max|c|][max a, max -a per stored slot], J each
   // tasks
   const int64_t* wg_task;           // n_wg + 1
   int32_t n_buckets;
@@ -138,7 +138,7 @@ struct dl_problem {
   float qscale[DL_MAX_FAMILIES] = {0, 0, 0, 0};
   int32_t max_degree = 0;
   // per-item extremes of the stored values (order-preserving uint encoding):
-  // [max(0, -c) over the item's users], then per stored slot [max a], [max -a]
+  // [max(0, -c) over the item's users], [max |c|], then per stored slot [max a], [max -a]
   unsigned* ext = nullptr;
   float* qs_dev = nullptr;   // DL_MAX_FAMILIES fixed-point scales of the last histogram pass
 
@@ -194,7 +194,7 @@ dl_status dl_grad_prepare(const dl_problem* P);
 // and the same for every instance of a batched pass (one block per entry).
 dl_status dl_launch_qscale(const dl_problem* P, const float* mu, double gamma);
 dl_status dl_launch_qscale_batch(const dl_grad_args* d_args, int n, hipStream_t st);
-// (Re)computes P->ext from the stored layout; c_only: only the c column.
+// (Re)computes P->ext from the stored layout; c_only: only the two c columns.
 dl_status dl_item_extremes(dl_problem* P, bool c_only);
 
 // Order-preserving encoding of floats as unsigned (max of codes = code of max).

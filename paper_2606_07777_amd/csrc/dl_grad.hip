@@ -324,7 +324,9 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
       }
       if constexpr ((MODE & M_OBJ) != 0) {
         // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
-        lobj += x * fmaf(0.5f * A.gamma, x, -A.gamma * fmaxf(v[k], -3.0e38f));
+        // (padding lanes hold v = -inf, whose term must not be formed)
+        const float term = x * fmaf(0.5f * A.gamma, x, -A.gamma * v[k]);
+        lobj += x > 0.f ? term : 0.f;
       }
       if constexpr ((MODE & M_REPAIR) != 0) {
         const float xt = s_rf[R.j[k]] * x;
@@ -494,7 +496,7 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
         }
       }
     }
-    if constexpr ((MODE & M_OBJ) != 0) lobj += x * fmaf(0.5f * A.gamma, x, -A.gamma * v);
+    if constexpr ((MODE & M_OBJ) != 0) lobj += x > 0.f ? x * fmaf(0.5f * A.gamma, x, -A.gamma * v) : 0.f;
     if constexpr ((MODE & M_REPAIR) != 0) {
       const float xt = s_rf[j] * x;
       lobj += xt * fmaf(0.5f * A.gamma, xt, c);
@@ -649,38 +651,56 @@ void set_attr_all() {
 }
 
 // Fixed-point scale of each family for one histogram pass.  For every item j
-// and user i, exactly (a >= 0 or not, lam of any sign):
+// and user i, with a of any sign and lam of any sign:
 //   v_ij = -(c_ij + sum_k a_kij mu_kj) / gamma
 //        <= (max_i(-c_ij)^+ + sum_k max(-amin_kj mu_kj, -amax_kj mu_kj)) / gamma,
-// x_ij <= min(z, max(0, v_ij)) (box, simplex <=; theta >= 0) or x_ij <= z
-// (simplex =), so |a_kij x_ij| <= B_k = max_j max|a_kj| xmax_j.  The scale
-// 2^(30 - ceil(log2 B_k)) keeps every fixed-point addend below 2^30 (FP32
-// rounding of v stays far inside the factor-2 headroom of int32) and makes
-// the grid as fine as the pass allows; it never drops below the coarsest
-// scale (max|a_k| * radius).  One block of 1024 lanes; deterministic.
+// and the FP32 value the pass forms differs from v_ij by at most
+// (m + 2) 2^-24 (max|c_j| + sum_k max|a_kj| |mu_kj|) / gamma + 2^-24 |v| (one
+// rounding per fused multiply-add, the sum and the scaling), so with the
+// margin below x_ij <= min(z, max(0, v) + margin) (box, simplex <=; theta >= 0)
+// or x_ij <= z (simplex =).  Hence |a_kij x_ij| <= B_k = max_j max|a_kj| xmax_j
+// and the scale 2^(30 - ceil(log2 B_k)) keeps every addend below 2^31 (the
+// relative roundings fit the factor-2 headroom above 2^30).  The grid is as
+// fine as the pass allows and never coarser than for max|a_k| * radius.  One
+// block of 1024 lanes; deterministic.
 __device__ void qscale_body(const dl_grad_args& A, float* out) {
   __shared__ float sh[1024];
   const int J = A.J, m = A.m;
-  const double inv_gamma = -(double)A.neg_inv_gamma;
+  const float ig = -A.neg_inv_gamma;
+  const float z = A.radius;
+  const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
+  const float ulp = 0x1p-24f * (float)(m + 4);
   float bk[DL_MAX_FAMILIES] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
   for (int j = threadIdx.x; j < J; j += blockDim.x) {
     const unsigned ec = A.ext[j];
-    if (ec == DL_ORD_NEG_INF) continue;  // no user is eligible for item j
-    double t = (double)dl_ord_dec(ec);
-    float amx[DL_MAX_FAMILIES], ang[DL_MAX_FAMILIES];
-    for (int k = 0; k < m; ++k) {
-      const int sl = A.a_slot[k];
-      amx[k] = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(1 + 2 * sl) * J + j]) : 1.f;
-      ang[k] = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(2 + 2 * sl) * J + j]) : -1.f;
-      const double mu = (double)A.mu[(size_t)k * J + j];
-      t += mu >= 0.0 ? (double)ang[k] * mu : (double)amx[k] * (-mu);
+    const float cneg = dl_ord_dec(ec), cabs = dl_ord_dec(A.ext[(size_t)J + j]);
+    float t = cneg, mag = cabs;
+    float aab[DL_MAX_FAMILIES];
+#pragma unroll
+    for (int k = 0; k < DL_MAX_FAMILIES; ++k) {
+      aab[k] = 0.f;
+      if (k < m) {
+        const int sl = A.a_slot[k];
+        const float amx = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(2 + 2 * sl) * J + j]) : 1.f;
+        const float ang = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(3 + 2 * sl) * J + j]) : -1.f;
+        const float mu = A.mu[(size_t)k * J + j];
+        t += mu >= 0.f ? ang * mu : amx * (-mu);
+        aab[k] = fmaxf(fabsf(amx), fabsf(ang));
+        mag += aab[k] * fabsf(mu);
+      }
     }
-    const double v = t * inv_gamma;
-    const double z = (double)A.radius;
-    const double xm = (A.proj == DL_PROJ_SIMPLEX_EQ) ? z : fmin(z, fmax(0.0, v));
-    for (int k = 0; k < m; ++k) bk[k] = fmaxf(bk[k], (float)(fmax(fabs((double)amx[k]), fabs((double)ang[k])) * xm));
+    // the bound itself in FP32: its own roundings are covered by the margin
+    const float v = t * ig;
+    const float xm = eq ? z : fminf(z, fmaxf(0.f, v) + ulp * (mag * ig + fabsf(v)) * 2.f);
+    const bool any = ec != DL_ORD_NEG_INF;  // some user is eligible for item j
+#pragma unroll
+    for (int k = 0; k < DL_MAX_FAMILIES; ++k)
+      if (k < m && any) bk[k] = fmaxf(bk[k], aab[k] * xm);
   }
-  for (int k = 0; k < m; ++k) {
+#pragma unroll
+  for (int k = 0; k < DL_MAX_FAMILIES; ++k) {
+    if (k >= m) break;
     sh[threadIdx.x] = bk[k];
     __syncthreads();
     for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
@@ -688,10 +708,10 @@ __device__ void qscale_body(const dl_grad_args& A, float* out) {
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const float B = sh[0] * (1.0f + 0x1p-20f);  // rounding of the bound itself
-      float q = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
-      q = fminf(fmaxf(q, A.qscale[k]), 0x1p60f);
-      out[k] = q;
+      const float B = sh[0] * (1.0f + 0x1p-16f);
+      float qv = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
+      qv = fminf(fmaxf(qv, A.qscale[k]), 0x1p60f);
+      out[k] = qv;
     }
     __syncthreads();
   }

@@ -126,7 +126,7 @@ __global__ void regather_c(const int64_t* orig_rp, const int64_t* new_rp, int64_
   if (bad) atomicOr(flag, 1);
 }
 
-// Per-item maximum of one stored quantity (kind 0: max(0, -c); 1: a; 2: -a)
+// Per-item maximum of one stored quantity (kind 0: max(0, -c); 1: a; 2: -a; 3: |c|)
 // in the order-preserving encoding: block-local LDS maxima, then one global
 // atomic maximum per item and block.
 template <typename TV>
@@ -137,7 +137,7 @@ __global__ void item_extreme(const int32_t* __restrict__ idx, const TV* __restri
   __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     float v = ld<TV>(val, e);
-    float q = kind == 0 ? fmaxf(0.f, -v) : (kind == 1 ? v : -v);
+    float q = kind == 0 ? fmaxf(0.f, -v) : (kind == 1 ? v : (kind == 2 ? -v : fabsf(v)));
     atomicMax(&s_ext[idx[e]], dl_ord_enc(q));
   }
   __syncthreads();
@@ -440,7 +440,7 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   DL_HIP_TRY(hipHostMalloc((void**)&P->cert_host, sizeof(double) * 16, hipHostMallocDefault));
   DL_TRY(dmalloc(P, &P->qs_dev, (size_t)DL_MAX_FAMILIES));
   DL_HIP_TRY(hipMemcpyAsync(P->qs_dev, P->qscale, sizeof(float) * DL_MAX_FAMILIES, hipMemcpyHostToDevice, st));
-  DL_TRY(dmalloc(P, &P->ext, (size_t)J * (size_t)(1 + 2 * P->n_stored)));
+  DL_TRY(dmalloc(P, &P->ext, (size_t)J * (size_t)(2 + 2 * P->n_stored)));
   DL_TRY(dl_item_extremes(P, false));
   DL_TRY(dl_grad_prepare(P));
   DL_HIP_TRY(hipStreamSynchronize(st));
@@ -519,7 +519,7 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** ou
 
 dl_status dl_item_extremes(dl_problem* P, bool c_only) {
   const int J = P->J;
-  const int n_q = c_only ? 1 : 1 + 2 * P->n_stored;
+  const int n_q = c_only ? 2 : 2 + 2 * P->n_stored;
   hipStream_t st = P->stream;
   const int64_t tot = (int64_t)J * n_q;
   hipLaunchKernelGGL(fill_u32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, P->ext, tot, DL_ORD_NEG_INF);
@@ -529,9 +529,10 @@ dl_status dl_item_extremes(dl_problem* P, bool c_only) {
   const size_t lds = sizeof(unsigned) * (size_t)J;
   const bool bf16 = P->storage == DL_BF16;
   for (int q = 0; q < n_q; ++q) {
-    const int kind = q == 0 ? 0 : (q % 2 == 1 ? 1 : 2);
-    const int slot = q == 0 ? 0 : (q - 1) / 2;
-    const void* val = q == 0 ? P->cval
+    // columns: max(0, -c), |c|, then max a and max -a of every stored slot
+    const int kind = q == 0 ? 0 : (q == 1 ? 3 : (q % 2 == 0 ? 1 : 2));
+    const int slot = q < 2 ? 0 : (q - 2) / 2;
+    const void* val = q < 2 ? P->cval
                              : (const void*)((const char*)P->aval + (size_t)slot * (size_t)(P->nnz + DL_PAD) *
                                                                        (bf16 ? 2 : 4));
     unsigned* out = P->ext + (size_t)q * J;
