@@ -114,6 +114,65 @@ def six_stage(prob, iters):
     return rows
 
 
+def ablation(args):
+    """The paper's two algorithmic ablations on its Appendix-A construction
+    (users = sources, items = destinations): |L - L_hat| of the dual value at
+    gamma = 0.01 every 10 iterations for (1) Jacobi row scaling on vs off at
+    fixed gamma = 0.01, and (2) gamma decayed 0.16 -> 0.01 (halved every 25
+    iterations, step scaled with gamma, momentum reset) vs fixed gamma = 0.01,
+    both with Jacobi.  L_hat is the dual value at gamma = 0.01 after a long
+    continuation solve.  Prints its own JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2606_07777_amd as dl
+    import workloads
+    t = time.time()
+    inst = workloads.appendix_a(seed=1, n_users=args.users, n_items=args.items, nu=args.nu)
+    log(f"appendix-A instance {args.users} x {args.items}, nnz {inst.nnz} in {time.time() - t:.1f}s")
+    torch.cuda.set_device(0)
+    g_final = 1e-2
+    n_it = args.ablation_iters
+    probs = {True: dl.Problem.from_instance(inst, jacobi=True), False: dl.Problem.from_instance(inst, jacobi=False)}
+    del inst
+    pj = probs[True]
+    # reference: long continuation solve, then the dual value at gamma = 0.01
+    lam_ref, st = pj.solve([0.16, 0.08, 0.04, 0.02, 0.01], [200, 200, 200, 200, args.ablation_ref_iters],
+                           check_every=0)
+    L_hat = pj.dual_grad(lam_ref, g_final, want_obj=True)[0]
+    log(f"L_hat = {L_hat:.10e} after {st['iters']} iterations")
+
+    def curve(prob, schedule):
+        s = prob.solver()
+        out = []
+        it = 0
+        for gamma, k in schedule:
+            s.set_stage(gamma, 1.0, True)
+            done = 0
+            while done < k:
+                step = min(10 - it % 10, k - done)
+                s.step(step)
+                done += step
+                it += step
+                if it % 10 == 0:
+                    L = prob.dual_grad(s.lam(), g_final, want_obj=True)[0]
+                    out.append([it, abs(L - L_hat)])
+        return out
+
+    fixed = [(g_final, n_it)]
+    decay = [(0.16, 25), (0.08, 25), (0.04, 25), (0.02, 25), (g_final, n_it - 100)]
+    res = {"metric": "|L - L_hat| of the dual value at gamma = 0.01 every 10 iterations", "L_hat": L_hat,
+           "jacobi_on": curve(probs[True], fixed), "jacobi_off": curve(probs[False], fixed),
+           "continuation": curve(probs[True], decay), "fixed_gamma": None,
+           "config": {"workload": f"appendix-A construction {args.users} x {args.items}, nu={args.nu}",
+                      "iterations": n_it}}
+    res["fixed_gamma"] = res["jacobi_on"]
+    for k in ("jacobi_on", "jacobi_off", "continuation"):
+        c = res[k]
+        log(f"{k}: " + ", ".join(f"{i}:{v:.3e}" for i, v in c[::max(1, len(c) // 8)]))
+    print(json.dumps(res), flush=True)
+
+
 def learned_eval(args, log=log):
     """Time to a 1e-4 certified gap on drifting days: cold start over the
     continuation schedule, the previous day's duals at the final gamma, and the
@@ -223,7 +282,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--workload", default="production", choices=["production", "tiny", "batch", "appendix_a"])
+    ap.add_argument("--workload", default="production",
+                    choices=["production", "tiny", "batch", "appendix_a", "ablation"])
+    ap.add_argument("--ablation-iters", type=int, default=500)
+    ap.add_argument("--ablation-ref-iters", type=int, default=4000)
     ap.add_argument("--nu", type=float, default=80.0, help="mean nonzeros per user of the appendix-A workload")
     ap.add_argument("--six-stage", type=int, default=0,
                     help="also run the six-stage gamma schedule 1e3..1e-2 with this many iterations per stage")
@@ -256,6 +318,8 @@ def main():
 
     if args.workload == "batch":
         return batch_bench(args)
+    if args.workload == "ablation":
+        return ablation(args)
 
     import numpy as np
     import torch

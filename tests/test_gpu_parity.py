@@ -206,6 +206,21 @@ def test_appendix_a_six_stage_schedule(dl, orc, wl):
     assert np.isfinite(cert["rel_gap"])
 
 
+def test_halving_continuation_matches_oracle(dl, orc, wl):
+    """The decay of the continuation ablation (gamma 0.16 -> 0.01, halved every
+    25 iterations, momentum reset, step scaled with gamma), no Jacobi and with
+    Jacobi, against the FP64 oracle run with the same schedule."""
+    inst = wl.appendix_a(seed=6, n_users=20_000, n_items=300, nu=10.0)
+    sched = dict(gammas=[0.16, 0.08, 0.04, 0.02, 0.01], iters=[25, 25, 25, 25, 50])
+    for jac in (True, False):
+        prob = dl.Problem.from_instance(inst, jacobi=jac)
+        lam, _ = prob.solve(**sched, check_every=0)
+        lo, _, _, _ = orc.solve(inst, sched["gammas"], sched["iters"], jacobi=jac, check_every=0)
+        rel = np.linalg.norm(lam.cpu().numpy() - lo) / max(np.linalg.norm(lo), 1e-300)
+        print(f"jacobi {jac}: |lam| {np.linalg.norm(lo):.3e} rel err {rel:.2e}")
+        assert rel <= 1e-5, (jac, rel)
+
+
 def test_bitwise_deterministic(dl, cases):
     inst, gamma = cases["production_small"]
     out = []
