@@ -30,7 +30,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dualip_oracle.c")
 _LIB = os.path.join(_HERE, "libdualip_oracle.so")
 
-PROJ = {"simplex_le": 0, "simplex_eq": 1, "box": 2}
+PROJ = {"simplex_le": 0, "simplex_eq": 1, "box": 2, "boxcut": 3}
 
 
 class _Inst(ctypes.Structure):
@@ -46,6 +46,7 @@ class _Inst(ctypes.Structure):
         ("proj", ctypes.c_int32),
         ("pad0", ctypes.c_int32),
         ("radius", ctypes.c_double),
+        ("upper", ctypes.c_double),
     ]
 
 
@@ -106,6 +107,8 @@ def _load():
         lib.orc_project_simplex.restype = None
         lib.orc_project_box.argtypes = [vp, ctypes.c_int64, ctypes.c_double, vp]
         lib.orc_project_box.restype = None
+        lib.orc_project_boxcut.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, vp]
+        lib.orc_project_boxcut.restype = None
         lib.orc_project_rows.argtypes = [vp, vp, vp]
         lib.orc_dual_grad_ex.argtypes = [vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp]
         lib.orc_primal.argtypes = [vp, vp, ctypes.c_double, vp, vp]
@@ -134,7 +137,7 @@ class _Bound:
         self.b = np.ascontiguousarray(inst.b, dtype=np.float64).reshape(-1)
         self.s = _Inst(int(inst.n_users), int(inst.n_items), int(inst.n_families), self.rp.ctypes.data,
                        self.idx.ctypes.data, self.c.ctypes.data, _p(self.a), self.b.ctypes.data,
-                       PROJ[inst.proj], 0, float(inst.radius))
+                       PROJ[inst.proj], 0, float(inst.radius), float(getattr(inst, "upper", 0.0) or 0.0))
         self.mJ = int(inst.n_families) * int(inst.n_items)
         self.nnz = int(self.rp[-1])
 
@@ -159,6 +162,14 @@ def project_box(v, u: float = 1.0) -> np.ndarray:
     v = np.ascontiguousarray(v, dtype=np.float64)
     x = np.empty_like(v)
     _load().orc_project_box(v.ctypes.data, v.size, float(u), x.ctypes.data)
+    return x
+
+
+def project_boxcut(v, u: float = 1.0, z: float = 1.0) -> np.ndarray:
+    """Pi onto {0 <= x <= u, sum x <= z} (box-cut primitive of Table 1)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    x = np.empty_like(v)
+    _load().orc_project_boxcut(v.ctypes.data, v.size, float(u), float(z), x.ctypes.data)
     return x
 
 

@@ -43,7 +43,7 @@
 #include <omp.h>
 #endif
 
-enum { ORC_SIMPLEX_LE = 0, ORC_SIMPLEX_EQ = 1, ORC_BOX = 2 };
+enum { ORC_SIMPLEX_LE = 0, ORC_SIMPLEX_EQ = 1, ORC_BOX = 2, ORC_BOXCUT = 3 };
 
 typedef struct {
   int64_t n_users;
@@ -56,7 +56,8 @@ typedef struct {
   const double* b;         /* m*J */
   int32_t proj;
   int32_t pad0;
-  double radius;
+  double radius;           /* z: simplex sum / box bound / box-cut sum */
+  double upper;            /* u of the box-cut set {0 <= x <= u, sum x <= z} */
 } orc_inst;
 
 #define ORC_CHUNKS 64
@@ -112,8 +113,73 @@ void orc_project_box(const double* v, int64_t d, double u, double* x) {
   for (int64_t e = 0; e < d; ++e) x[e] = v[e] < 0.0 ? 0.0 : (v[e] > u ? u : v[e]);
 }
 
+static int cmp_asc(const void* p, const void* q) {
+  double x = *(const double*)p, y = *(const double*)q;
+  return (x > y) - (x < y);
+}
+
+static double boxcut_sum(const double* v, int64_t d, double u, double theta) {
+  double f = 0.0;
+  for (int64_t e = 0; e < d; ++e) {
+    double y = v[e] - theta;
+    f += y < 0.0 ? 0.0 : (y > u ? u : y);
+  }
+  return f;
+}
+
+/*
+ * Euclidean projection onto the box-cut set {0 <= x <= u, sum x <= z} (the
+ * ProjectionMap primitive named in Table 1).  KKT: x = clamp(v - theta, 0, u)
+ * with theta = 0 if clamp(v, 0, u) sums to at most z, else theta > 0 with
+ * f(theta) = sum clamp(v - theta, 0, u) = z.  f is continuous, nonincreasing
+ * and linear between the breakpoints {v_e, v_e - u}; bisection over the sorted
+ * breakpoints finds the piece where f crosses z, and on that piece the free
+ * coordinates F and capped coordinates C give theta = (|C| u + sum_F v - z) / |F|.
+ */
+void orc_project_boxcut(const double* v, int64_t d, double u, double z, double* x) {
+  if (d <= 0) return;
+  if (boxcut_sum(v, d, u, 0.0) <= z) {
+    for (int64_t e = 0; e < d; ++e) x[e] = v[e] < 0.0 ? 0.0 : (v[e] > u ? u : v[e]);
+    return;
+  }
+  double* bp = (double*)malloc(sizeof(double) * (size_t)(2 * d + 1));
+  int64_t n = 0;
+  bp[n++] = 0.0;
+  for (int64_t e = 0; e < d; ++e) {
+    if (v[e] > 0.0) bp[n++] = v[e];
+    if (v[e] - u > 0.0) bp[n++] = v[e] - u;
+  }
+  qsort(bp, (size_t)n, sizeof(double), cmp_asc);
+  /* f(bp[0] = 0) > z and f(bp[n-1] = max v) = 0 <= z: find lo < hi adjacent with f(lo) > z >= f(hi) */
+  int64_t lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) / 2;
+    if (boxcut_sum(v, d, u, bp[mid]) > z) lo = mid;
+    else hi = mid;
+  }
+  double theta;
+  if (bp[hi] <= bp[lo]) {
+    theta = bp[hi];
+  } else {
+    const double tm = 0.5 * (bp[lo] + bp[hi]);
+    double cnt = 0.0, sfree = 0.0, capped = 0.0;
+    for (int64_t e = 0; e < d; ++e) {
+      double y = v[e] - tm;
+      if (y >= u) capped += u;
+      else if (y > 0.0) { cnt += 1.0; sfree += v[e]; }
+    }
+    theta = cnt > 0.0 ? (capped + sfree - z) / cnt : bp[hi];
+  }
+  free(bp);
+  for (int64_t e = 0; e < d; ++e) {
+    double y = v[e] - theta;
+    x[e] = y < 0.0 ? 0.0 : (y > u ? u : y);
+  }
+}
+
 static void project_row(const orc_inst* P, const double* v, int64_t d, double* x) {
   if (P->proj == ORC_BOX) orc_project_box(v, d, P->radius, x);
+  else if (P->proj == ORC_BOXCUT) orc_project_boxcut(v, d, P->upper, P->radius, x);
   else orc_project_simplex(v, d, P->radius, P->proj == ORC_SIMPLEX_EQ, x);
 }
 

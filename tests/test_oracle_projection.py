@@ -150,3 +150,79 @@ def test_project_rows_blockwise(orc, wl):
         s, e = rp[i], rp[i + 1]
         np.testing.assert_allclose(x[s:e], brute_simplex(v[s:e], 1.0, False) if e - s <= 8
                                    else orc.project_simplex(v[s:e], 1.0), atol=1e-12)
+
+
+def brute_boxcut(v, u, z):
+    """argmin 1/2||x - v||^2 over {0 <= x <= u, sum x <= z} by enumerating, for
+    every coordinate, whether it sits at 0, at u or strictly between.  With the
+    sum constraint loose the candidate is clamp(v, 0, u); with it tight the free
+    coordinates F and capped coordinates C fix the multiplier
+    t = (|C| u + sum_F v - z) / |F| and x_F = v_F - t.  Every feasible candidate
+    is scored; the strictly convex problem has its minimiser among them."""
+    v = np.asarray(v, dtype=float)
+    d = v.size
+    cands = []
+    x0 = np.clip(v, 0.0, u)
+    if x0.sum() <= z + 1e-12:
+        cands.append(x0)
+    for states in itertools.product((0, 1, 2), repeat=d):
+        F = [e for e in range(d) if states[e] == 1]
+        C = [e for e in range(d) if states[e] == 2]
+        if not F:
+            continue
+        t = (len(C) * u + v[F].sum() - z) / len(F)
+        x = np.zeros(d)
+        x[C] = u
+        x[F] = v[F] - t
+        if t >= -1e-12 and np.all(x >= -1e-12) and np.all(x <= u + 1e-12) and x.sum() <= z + 1e-9:
+            cands.append(np.clip(x, 0.0, u))
+    return min(cands, key=lambda x: 0.5 * np.sum((x - v) ** 2))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 6])
+def test_boxcut_matches_state_enumeration(orc, d):
+    rng = np.random.default_rng(100 + d)
+    for _ in range(40):
+        v = rng.normal(size=d) * 2
+        u = float(rng.uniform(0.1, 1.5))
+        z = float(rng.uniform(0.2, 3.0))
+        np.testing.assert_allclose(orc.project_boxcut(v, u, z), brute_boxcut(v, u, z), atol=1e-10)
+
+
+def test_boxcut_special_cases(orc):
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        d = int(rng.integers(1, 40))
+        v = rng.normal(size=d) * 3
+        z = float(rng.uniform(0.1, 2.0))
+        # u >= z: the cap is implied by the sum, the set is the simplex <= z
+        np.testing.assert_allclose(orc.project_boxcut(v, z * 1.5, z), orc.project_simplex(v, z), atol=1e-12)
+        # z >= d u: the sum is implied by the cap, the set is the box
+        u = float(rng.uniform(0.1, 1.0))
+        np.testing.assert_allclose(orc.project_boxcut(v, u, d * u + 1.0), orc.project_box(v, u), atol=0)
+
+
+def test_boxcut_kkt_and_generic_solver(orc):
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(8)
+    for trial in range(30):
+        d = int(rng.integers(2, 30))
+        v = rng.normal(size=d) * 2 + 0.5
+        u, z = float(rng.uniform(0.2, 1.0)), float(rng.uniform(0.5, 4.0))
+        x = orc.project_boxcut(v, u, z)
+        # KKT: x = clamp(v - t, 0, u) for one t >= 0, complementary to the sum constraint
+        assert np.all(x >= 0) and np.all(x <= u) and x.sum() <= z + 1e-12
+        free = (x > 1e-12) & (x < u - 1e-12)
+        if free.any():
+            t = np.mean(v[free] - x[free])
+            np.testing.assert_allclose(v[free] - x[free], t, atol=1e-10)
+            assert t >= -1e-10
+            np.testing.assert_allclose(np.clip(v - t, 0, u), x, atol=1e-10)
+            if t > 1e-10:
+                assert abs(x.sum() - z) <= 1e-10
+        if trial < 10:
+            r = minimize(lambda y: 0.5 * np.sum((y - v) ** 2), np.full(d, min(u, z / d) * 0.5),
+                         jac=lambda y: y - v, bounds=[(0, u)] * d,
+                         constraints=[{"type": "ineq", "fun": lambda y: z - y.sum(), "jac": lambda y: -np.ones(d)}],
+                         method="SLSQP", options={"ftol": 1e-14, "maxiter": 500})
+            np.testing.assert_allclose(x, r.x, atol=1e-6)

@@ -33,7 +33,7 @@ def qp_solve(inst, gamma):
             S[i, rp[i]:rp[i + 1]] = 1.0
         kind = "eq" if inst.proj == "simplex_eq" else "ineq"
         cons.append({"type": kind, "fun": lambda x: inst.radius - S @ x, "jac": lambda x: -S})
-        bounds = [(0, None)] * n
+        bounds = [(0, inst.upper if inst.proj == "boxcut" else None)] * n
     else:
         bounds = [(0, inst.radius)] * n
     res = minimize(lambda x: c @ x + 0.5 * gamma * x @ x, np.zeros(n), jac=lambda x: c + gamma * x,
@@ -48,6 +48,7 @@ def qp_solve(inst, gamma):
     dict(seed=21, n_users=25, n_items=5, max_degree=4, b_scale=0.3),
     dict(seed=22, n_users=20, n_items=4, max_degree=4, n_families=2, a_ones=False, b_scale=0.35),
     dict(seed=23, n_users=20, n_items=5, max_degree=4, proj="box", b_scale=0.3),
+    dict(seed=24, n_users=20, n_items=5, max_degree=4, proj="boxcut", radius=1.0, upper=0.4, b_scale=0.3),
 ])
 def test_converged_matches_qp(orc, wl, kw):
     inst = wl.random_small(**kw)

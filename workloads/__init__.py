@@ -154,6 +154,7 @@ class Instance:
     proj: str = "simplex_le"
     radius: float = 1.0
     meta: dict = field(default_factory=dict)
+    upper: float = 0.0   # u of the box-cut set {0 <= x <= u, sum x <= radius}
 
     @property
     def nnz(self) -> int:
@@ -178,7 +179,7 @@ class Instance:
         a = None if self.a is None else np.ascontiguousarray(self.a[:, s:e])
         return Instance(self.name + f"[{first}:{first + count}]", count, self.n_items, self.n_families,
                         rp, self.item_idx[s:e].copy(), self.c[s:e].copy(), a, self.b.copy(),
-                        self.proj, self.radius, dict(self.meta))
+                        self.proj, self.radius, dict(self.meta), self.upper)
 
 
 def _generate(n_users, n_items, seed, deg_kind, deg_p1, deg_p2, deg_min, deg_max, item_kind,
@@ -322,8 +323,9 @@ def cadence_next(prev: Instance, day: int) -> Instance:
 
 def random_small(seed: int, n_users: int, n_items: int, max_degree: int, n_families: int = 1,
                  proj: str = "simplex_le", radius: float = 1.0, a_ones: bool = True,
-                 b_scale: float = 0.3) -> Instance:
-    """Small random instance for property tests (any projection kind, m families)."""
+                 b_scale: float = 0.3, upper: float = 0.0) -> Instance:
+    """Small random instance for property tests (any projection kind, m families;
+    ``upper`` is the cap u of the box-cut set)."""
     rp, idx, c, a_ln, _ = _generate(n_users, n_items, seed, DEG_LOGNORMAL, math.log(max(2, max_degree) / 2),
                                     0.7, 1, max_degree, ITEM_UNIFORM, 0.0, C_NEG_UNIFORM,
                                     fam_kinds=tuple(A_ONES if (a_ones and k == 0) else A_LOGNORMAL
@@ -346,4 +348,4 @@ def random_small(seed: int, n_users: int, n_items: int, max_degree: int, n_famil
                          for k in range(n_families)])
     b = b_scale * sums * radius
     return Instance(f"random_small{seed}", n_users, n_items, n_families, rp, idx, c, a, b, proj, radius,
-                    {"seed": seed})
+                    {"seed": seed}, upper)
