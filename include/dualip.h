@@ -55,7 +55,7 @@ typedef enum {
 } dl_status;
 
 /* Per-user simple set (Section 3.3). radius is z for the simplices, u for the box. */
-typedef enum { DL_PROJ_SIMPLEX_LE = 0, DL_PROJ_SIMPLEX_EQ = 1, DL_PROJ_BOX = 2 } dl_proj_kind;
+typedef enum { DL_PROJ_SIMPLEX_LE = 0, DL_PROJ_SIMPLEX_EQ = 1, DL_PROJ_BOX = 2, DL_PROJ_BOXCUT = 3 } dl_proj_kind;
 
 /* Storage of c and a in device memory. DL_BF16 rounds (to nearest even) at
  * create time; projection and accumulation stay FP32 / fixed point, the dual
@@ -88,7 +88,8 @@ typedef struct {
   const double* b;          /* host, m*J, family-major right-hand side */
   int32_t proj;             /* dl_proj_kind */
   int32_t storage;          /* dl_storage */
-  double radius;            /* z (simplex) or u (box), > 0 */
+  double radius;            /* z (simplex, box-cut sum) or u (box), > 0 */
+  double upper;             /* u of the box-cut set {0 <= x <= u, sum x <= z} (DL_PROJ_BOXCUT), > 0 */
   int32_t jacobi;           /* 1: Jacobi row scaling in the solver (Appendix C) */
   int32_t wg_per_cu;        /* gradient-pass workgroups per compute unit, 0 = default (4) */
   int32_t layout;           /* dl_layout: user-to-lane mapping of the gradient pass */

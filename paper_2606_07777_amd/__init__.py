@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("DUALIP_LIB", os.path.join(HERE, "libdualip.so"))
 DL_OK, DL_NOT_CONVERGED = 0, 1
 STATUS = {0: "DL_OK", 1: "DL_NOT_CONVERGED", -1: "DL_EINVAL", -2: "DL_ENOMEM", -3: "DL_EHIP",
           -4: "DL_EUNSUPPORTED", -5: "DL_DIVERGED", -6: "DL_NUMERIC"}
-PROJ = {"simplex_le": 0, "simplex_eq": 1, "box": 2}
+PROJ = {"simplex_le": 0, "simplex_eq": 1, "box": 2, "boxcut": 3}
 STORAGE = {"f32": 0, "bf16": 1}
 LAYOUT = {"bucketed": 0, "wavefront": 1}
 
@@ -46,6 +46,7 @@ class dl_problem_desc(ctypes.Structure):
         ("proj", ctypes.c_int32),
         ("storage", ctypes.c_int32),
         ("radius", ctypes.c_double),
+        ("upper", ctypes.c_double),
         ("jacobi", ctypes.c_int32),
         ("wg_per_cu", ctypes.c_int32),
         ("layout", ctypes.c_int32),
@@ -216,7 +217,7 @@ class Problem:
     """
 
     def __init__(self, n_users, n_items, n_families, row_ptr, item_idx, c, a, b, proj="simplex_le",
-                 radius=1.0, storage="f32", jacobi=True, wg_per_cu=0, stream=None, layout="bucketed"):
+                 radius=1.0, storage="f32", jacobi=True, wg_per_cu=0, stream=None, layout="bucketed", upper=0.0):
         import torch
         self.torch = torch
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -237,7 +238,7 @@ class Problem:
         self.stream = _stream(torch, stream)
         desc = dl_problem_desc(self.I, self.J, self.m, _ptr(self._rp), _ptr(self._idx), _ptr(self._c),
                                _ptr(self._a), bh.ctypes.data, PROJ[proj], STORAGE[storage], float(radius),
-                               int(jacobi), int(wg_per_cu), LAYOUT[layout], self.stream)
+                               float(upper), int(jacobi), int(wg_per_cu), LAYOUT[layout], self.stream)
         h = ctypes.c_void_p()
         _check(load().dl_problem_create(ctypes.byref(desc), ctypes.byref(h)))
         self.handle = h
@@ -249,7 +250,8 @@ class Problem:
     def from_instance(cls, inst, storage="f32", jacobi=True, wg_per_cu=0, stream=None, layout="bucketed"):
         """From any object with the attributes of a CSR matching instance."""
         return cls(inst.n_users, inst.n_items, inst.n_families, inst.row_ptr, inst.item_idx, inst.c, inst.a,
-                   inst.b, inst.proj, inst.radius, storage, jacobi, wg_per_cu, stream, layout)
+                   inst.b, inst.proj, inst.radius, storage, jacobi, wg_per_cu, stream, layout,
+                   float(getattr(inst, "upper", 0.0) or 0.0))
 
     def close(self):
         if getattr(self, "handle", None):

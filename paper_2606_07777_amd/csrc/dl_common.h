@@ -102,6 +102,7 @@ struct dl_grad_args {
   int32_t proj;                     // dl_proj_kind
   dl_bucket bk[DL_MAX_BUCKETS];
   float radius;
+  float upper;                      // u of the box-cut set
   // iteration inputs
   float neg_inv_gamma;
   float gamma;
@@ -130,6 +131,7 @@ struct dl_problem {
   int64_t I = 0, I_active = 0, nnz = 0;
   int32_t J = 0, m = 0, proj = 0, storage = 0, jacobi = 0;
   double radius = 1.0;
+  double upper = 0.0;    // u of the box-cut set
   int kmax = 16;
   int mf = 1;            // compiled family bound of the kernel variant (1 or 4)
   bool has_a = false;    // at least one stored family

@@ -240,6 +240,88 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
   }
 }
 
+// Box-cut set {0 <= x <= u, sum x <= z} (Table 1's third projection kind):
+// x = clamp(v - theta, 0, u), theta = 0 when clamp(v, 0, u) sums to at most
+// z, else the root of f(theta) = sum clamp(v - theta, 0, u) - z, which is
+// nonincreasing and linear between the breakpoints {v, v - u}.  Evaluation at
+// theta: f, the count of coordinates free just right of theta (0 < v - theta
+// <= u: one sitting at its cap starts to move) and the next breakpoint above
+// theta.
+template <int GLOG, int KMAX, bool HAS_A>
+__device__ __forceinline__ void boxcut_eval(const float (&v)[KMAX], int K, float theta, float u, float& f,
+                                            float& cnt, float& nb) {
+  f = 0.f;
+  cnt = 0.f;
+  nb = INFINITY;
+  DL_FOR_KC(k, KMAX, K) {
+    {
+      const float t = v[k] - theta;
+      f += fminf(fmaxf(t, 0.f), u);
+      cnt += (t > 0.f && t <= u) ? 1.f : 0.f;
+      nb = fminf(nb, t > u ? v[k] - u : (t > 0.f ? v[k] : INFINITY));
+    }
+  }
+  f = gsum<GLOG>(f);
+  cnt = gsum<GLOG>(cnt);
+  nb = gmin<GLOG>(nb);
+}
+
+// theta of every lane group of the wavefront: Newton steps from the left end
+// of a bracket [lo, hi] (exact once the step stays inside the piece that
+// starts at lo), the secant of the bracket once no breakpoint lies inside it
+// (exact as well), bisection otherwise.  Every lane runs every round (the
+// group reductions need the whole wavefront).
+template <int GLOG, int KMAX, bool HAS_A>
+__device__ __forceinline__ float boxcut_theta(const float (&v)[KMAX], int K, float z, float u) {
+  float flo, clo, nblo;
+  boxcut_eval<GLOG, KMAX, HAS_A>(v, K, 0.f, u, flo, clo, nblo);
+  flo -= z;
+  float m1 = -INFINITY;
+  DL_FOR_KC(k, KMAX, K) m1 = fmaxf(m1, v[k]);
+  m1 = gmax<GLOG>(m1);
+  bool done = !(flo > 0.f);  // clamp(v, 0, u) already fits (or no user here)
+  float theta = 0.f, lo = 0.f, hi = m1, fhi = -z;
+  for (int it = 0; it < 64 && __any(!done); ++it) {
+    float cand = 0.5f * (lo + hi);
+    if (!done) {
+      if (clo > 0.f) {
+        const float tn = lo + flo * __builtin_amdgcn_rcpf(clo);
+        if (tn <= nblo) {
+          theta = tn;  // the linear piece at lo reaches z: exact
+          done = true;
+        }
+        cand = tn;
+      } else {
+        cand = nblo;
+      }
+      if (!done && nblo >= hi) {
+        theta = lo + (hi - lo) * (flo / (flo - fhi));  // f is linear on [lo, hi]
+        done = true;
+      }
+      if (!(cand > lo && cand < hi)) cand = 0.5f * (lo + hi);
+    }
+    float f, c, nb;
+    boxcut_eval<GLOG, KMAX, HAS_A>(v, K, cand, u, f, c, nb);
+    f -= z;
+    if (!done) {
+      if (fabsf(f) <= z * 0x1p-22f) {
+        theta = cand;
+        done = true;
+      } else if (f > 0.f) {
+        lo = cand;
+        flo = f;
+        clo = c;
+        nblo = nb;
+      } else {
+        hi = cand;
+        fhi = f;
+      }
+    }
+  }
+  if (!done) theta = clo > 0.f ? lo + flo / clo : lo;
+  return theta;
+}
+
 // Projects the task's rows (v in R.c) and accumulates what MODE asks.
 template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
@@ -252,8 +334,11 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   float (&v)[KMAX] = R.c;
   const float z = A.radius;
   const bool box = (A.proj == DL_PROJ_BOX);
+  const bool boxcut = (A.proj == DL_PROJ_BOXCUT);
   float theta = 0.f;
-  if (!box) {
+  if (boxcut) {
+    theta = boxcut_theta<GLOG, KMAX, HAS_A>(v, K, z, A.upper);
+  } else if (!box) {
     // pass A: largest two entries, positive part and its count
     float m1 = -INFINITY, m2 = -INFINITY, sp = 0.f, cp = 0.f;
     DL_FOR_KC(k, KMAX, K) {
@@ -337,6 +422,9 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   // one loop per projection kind, so the kind is not re-tested per element
   if (box) {
     DL_FOR_KC(k, KMAX, K) emit(k, fminf(fmaxf(v[k], 0.f), z));
+  } else if (boxcut) {
+    const float u = A.upper;
+    DL_FOR_KC(k, KMAX, K) emit(k, fminf(fmaxf(v[k] - theta, 0.f), u));
   } else {
     DL_FOR_KC(k, KMAX, K) emit(k, fmaxf(v[k] - theta, 0.f));
   }
@@ -443,11 +531,74 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
   const int64_t os = (MODE & (M_VIN | M_XOUT)) ? A.orig_rp[u] : 0;
   const float z = A.radius;
   const bool box = (A.proj == DL_PROJ_BOX);
+  const bool boxcut = (A.proj == DL_PROJ_BOXCUT);
+  const float ucap = A.upper;
   int j = 0;
   float c = 0.f;
   float af[HAS_A ? MF : 1];
   float theta = 0.f;
-  if (!box) {
+  if (boxcut) {
+    // same bracketed Newton iteration as the group path, one wavefront per row
+    auto eval = [&](float th, float& f, float& cnt, float& nb) {
+      f = 0.f;
+      cnt = 0.f;
+      nb = INFINITY;
+      for (int e = lane; e < d; e += 64) {
+        const float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
+        const float t = v - th;
+        f += fminf(fmaxf(t, 0.f), ucap);
+        cnt += (t > 0.f && t <= ucap) ? 1.f : 0.f;
+        nb = fminf(nb, t > ucap ? v - ucap : (t > 0.f ? v : INFINITY));
+      }
+      f = gsum<6>(f);
+      cnt = gsum<6>(cnt);
+      nb = gmin<6>(nb);
+    };
+    float flo, clo, nblo;
+    eval(0.f, flo, clo, nblo);
+    flo -= z;
+    if (flo > 0.f) {
+      float vmax = -INFINITY;
+      for (int e = lane; e < d; e += 64) vmax = fmaxf(vmax, long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af));
+      float lo = 0.f, hi = gmax<6>(vmax), fhi = -z;
+      bool done = false;
+      for (int it = 0; it < 64 && !done; ++it) {
+        float cand;
+        if (clo > 0.f) {
+          cand = lo + flo / clo;
+          if (cand <= nblo) {
+            theta = cand;
+            done = true;
+            break;
+          }
+        } else {
+          cand = nblo;
+        }
+        if (nblo >= hi) {
+          theta = lo + (hi - lo) * (flo / (flo - fhi));  // f is linear on [lo, hi]
+          done = true;
+          break;
+        }
+        if (!(cand > lo && cand < hi)) cand = 0.5f * (lo + hi);
+        float f, cn, nb;
+        eval(cand, f, cn, nb);
+        f -= z;
+        if (fabsf(f) <= z * 0x1p-22f) {
+          theta = cand;
+          done = true;
+        } else if (f > 0.f) {
+          lo = cand;
+          flo = f;
+          clo = cn;
+          nblo = nb;
+        } else {
+          hi = cand;
+          fhi = f;
+        }
+      }
+      if (!done) theta = clo > 0.f ? lo + flo / clo : lo;
+    }
+  } else if (!box) {
     float vmax = -INFINITY, sp = 0.f, cp = 0.f;
     for (int e = lane; e < d; e += 64) {
       float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
@@ -484,7 +635,7 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
   float lobj = 0.f;
   for (int e = lane; e < d; e += 64) {
     float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
-    float x = box ? fminf(fmaxf(v, 0.f), z) : fmaxf(v - theta, 0.f);
+    float x = box ? fminf(fmaxf(v, 0.f), z) : (boxcut ? fminf(fmaxf(v - theta, 0.f), ucap) : fmaxf(v - theta, 0.f));
     if constexpr ((MODE & M_XOUT) != 0) A.x_out[os + e] = x;
     if constexpr ((MODE & M_HIST) != 0) {
 #pragma unroll
@@ -799,6 +950,7 @@ dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamm
   for (size_t i = 0; i < P->buckets.size(); ++i) A.bk[i] = P->buckets[i];
   A.proj = P->proj;
   A.radius = (float)P->radius;
+  A.upper = (float)P->upper;
   A.neg_inv_gamma = (float)(-1.0 / gamma);
   A.gamma = (float)gamma;
   A.mu = mu;

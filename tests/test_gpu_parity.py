@@ -37,11 +37,14 @@ def _cases(wl):
         "explicit_a": (wl.random_small(54, 4000, 500, 300, a_ones=False), 1e-2),
         "production_small": (wl.production(n_users=100_000, n_items=10_000), 1e-2),
         "appendix_a": (wl.appendix_a(seed=3, n_users=20_000, n_items=300, nu=12.0), 1.0),
+        "boxcut": (wl.random_small(55, 6000, 400, 300, proj="boxcut", radius=1.0, upper=0.3, b_scale=0.2), 1e-2),
+        "boxcut_long_rows": (wl.random_small(56, 3000, 3500, 3000, proj="boxcut", radius=2.0, upper=0.25,
+                                             b_scale=0.2), 5e-2),
     }
 
 
 CASE_NAMES = ["tiny_plain_binding", "all_buckets_long_rows", "two_family_box", "simplex_eq", "explicit_a",
-              "production_small", "appendix_a"]
+              "production_small", "appendix_a", "boxcut", "boxcut_long_rows"]
 
 
 @pytest.fixture(scope="module")
@@ -101,7 +104,8 @@ def test_dual_grad_matches_oracle(dl, orc, cases, name, layout):
     print(f"{name}: nnz {inst.nnz} x err {xerr.max():.2e} grad rel {rel:.2e} dual rel {abs(g - go) / abs(go):.2e}")
 
 
-@pytest.mark.parametrize("name", ["tiny_plain_binding", "all_buckets_long_rows", "simplex_eq", "two_family_box"])
+@pytest.mark.parametrize("name", ["tiny_plain_binding", "all_buckets_long_rows", "simplex_eq", "two_family_box",
+                                  "boxcut", "boxcut_long_rows"])
 def test_project_matches_oracle(dl, orc, cases, name):
     import torch
     inst, _ = cases[name]
@@ -204,6 +208,21 @@ def test_appendix_a_six_stage_schedule(dl, orc, wl):
     cert = s.certificate()
     print(f"certificate after the schedule: {cert}")
     assert np.isfinite(cert["rel_gap"])
+
+
+def test_boxcut_continuation_solve_matches_oracle(dl, orc, wl):
+    inst = wl.random_small(57, 20_000, 200, 60, proj="boxcut", radius=1.0, upper=0.35, b_scale=0.02)
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    sched = dict(gammas=[1e-1, 1e-2], iters=[200, 200])
+    lam, _ = prob.solve(**sched, check_every=0)
+    lo, _, _, _ = orc.solve(inst, sched["gammas"], sched["iters"], jacobi=True, check_every=0)
+    rel = np.linalg.norm(lam.cpu().numpy() - lo) / max(np.linalg.norm(lo), 1e-300)
+    print(f"box-cut trajectory: |lam| {np.linalg.norm(lo):.3e} rel err {rel:.2e}")
+    assert np.linalg.norm(lo) > 0 and rel <= 1e-5
+    s = prob.solver(lam)
+    s.set_stage(1e-2, 1.0, True)
+    c = s.certificate()
+    assert np.isfinite(c["rel_gap"]) and c["rel_gap"] >= -1e-6
 
 
 def test_halving_continuation_matches_oracle(dl, orc, wl):
