@@ -44,7 +44,7 @@ class _Inst(ctypes.Structure):
         ("a", ctypes.c_void_p),
         ("b", ctypes.c_void_p),
         ("proj", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("eq_mask", ctypes.c_int32),
         ("radius", ctypes.c_double),
         ("upper", ctypes.c_double),
     ]
@@ -137,7 +137,8 @@ class _Bound:
         self.b = np.ascontiguousarray(inst.b, dtype=np.float64).reshape(-1)
         self.s = _Inst(int(inst.n_users), int(inst.n_items), int(inst.n_families), self.rp.ctypes.data,
                        self.idx.ctypes.data, self.c.ctypes.data, _p(self.a), self.b.ctypes.data,
-                       PROJ[inst.proj], 0, float(inst.radius), float(getattr(inst, "upper", 0.0) or 0.0))
+                       PROJ[inst.proj], int(getattr(inst, "eq_families", 0) or 0), float(inst.radius),
+                       float(getattr(inst, "upper", 0.0) or 0.0))
         self.mJ = int(inst.n_families) * int(inst.n_items)
         self.nnz = int(self.rp[-1])
 

@@ -55,7 +55,7 @@ typedef struct {
   const float* a;          /* m*nnz family-major, or NULL: every a_kij = 1 */
   const double* b;         /* m*J */
   int32_t proj;
-  int32_t pad0;
+  int32_t eq_mask;         /* bit k: family k holds equality rows A_k x = b_k (free duals) */
   double radius;           /* z: simplex sum / box bound / box-cut sum */
   double upper;            /* u of the box-cut set {0 <= x <= u, sum x <= z} */
 } orc_inst;
@@ -350,8 +350,9 @@ typedef struct {
 /*
  * At lam: x = x*(lam); r_j = min_k min(1, b_kj / (A_k x)_j) (1 when (A_k x)_j
  * <= b_kj); x~_ij = r_j x_ij is feasible when a >= 0, b >= 0 and C is closed
- * under scaling toward 0 (simplex-LE, box).  Weak duality gives
- * g(lam) <= P(x~).
+ * under scaling toward 0 (simplex-LE, box, box-cut).  Weak duality gives
+ * g(lam) <= P(x~).  Equality rows have no such repair: with any of them the
+ * gap is NaN and the slack is max |A x - b| over them.
  */
 int orc_certificate(const orc_inst* P, const double* lam, double gamma, orc_stats* st) {
   const int64_t nnz = P->row_ptr[P->n_users];
@@ -368,9 +369,10 @@ int orc_certificate(const orc_inst* P, const double* lam, double gamma, orc_stat
     for (int32_t j = 0; j < J; ++j) {
       int64_t q = (int64_t)k * J + j;
       double viol = ax[q] - P->b[q];
-      if (viol > slack) slack = viol;
+      const int eq = (P->eq_mask >> k) & 1;
+      if ((eq ? fabs(viol) : viol) > slack) slack = eq ? fabs(viol) : viol;
       lg -= lam[q] * viol;
-      if (ax[q] > P->b[q]) {
+      if (!eq && ax[q] > P->b[q]) {
         double f = P->b[q] > 0.0 ? P->b[q] / ax[q] : 0.0;
         if (f < r[j]) r[j] = f;
       }
@@ -385,7 +387,7 @@ int orc_certificate(const orc_inst* P, const double* lam, double gamma, orc_stat
   st->gamma = gamma;
   st->dual_obj = gval;
   st->primal_obj = pobj;
-  st->rel_gap = (pobj - gval) / fmax(1.0, fabs(gval));
+  st->rel_gap = (P->eq_mask & ((1 << m) - 1)) ? NAN : (pobj - gval) / fmax(1.0, fabs(gval));
   st->max_slack = slack;
   st->lagr_gap = lg;
   free(x); free(ax); free(r);
@@ -427,7 +429,9 @@ int orc_solve(const orc_inst* P, const orc_solve_opts* o, const double* lam0, do
   double* gr = (double*)malloc(sizeof(double) * (size_t)mJ);
   double* lo = (double*)malloc(sizeof(double) * (size_t)mJ);
   for (int64_t r = 0; r < mJ; ++r) {
-    lp[r] = lam0 ? lam0[r] / D[r] : 0.0;
+    const int eq = (P->eq_mask >> (int)(r / J)) & 1;
+    double l = lam0 ? lam0[r] / D[r] : 0.0;
+    lp[r] = (eq || l > 0.0) ? l : 0.0;
     yp[r] = lp[r];
   }
   int64_t it = 0, snap = 0;
@@ -449,7 +453,8 @@ int orc_solve(const orc_inst* P, const orc_solve_opts* o, const double* lam0, do
       const double beta = (tk - 1.0) / tn;
       for (int64_t r = 0; r < mJ; ++r) {
         double step = yp[r] + eta * D[r] * gr[r]; /* ascent on the scaled dual */
-        double ln = step > 0.0 ? step : 0.0;      /* lam' >= 0 */
+        const int eq = (P->eq_mask >> (int)(r / J)) & 1;
+        double ln = (eq || step > 0.0) ? step : 0.0; /* lam' >= 0 on inequality rows, free on equality rows */
         lo[r] = lp[r];
         lp[r] = ln;
         yp[r] = ln + beta * (ln - lo[r]);

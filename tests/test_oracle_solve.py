@@ -26,7 +26,15 @@ def qp_solve(inst, gamma):
     c = inst.c.astype(np.float64)
     n = inst.nnz
     rp = inst.row_ptr
-    cons = [{"type": "ineq", "fun": lambda x: b - A @ x, "jac": lambda x: -A}]
+    eqr = np.zeros(A.shape[0], dtype=bool)
+    for k in range(inst.n_families):
+        if (getattr(inst, "eq_families", 0) >> k) & 1:
+            eqr[k * inst.n_items:(k + 1) * inst.n_items] = True
+    cons = []
+    if (~eqr).any():
+        cons.append({"type": "ineq", "fun": lambda x: b[~eqr] - A[~eqr] @ x, "jac": lambda x: -A[~eqr]})
+    if eqr.any():
+        cons.append({"type": "eq", "fun": lambda x: b[eqr] - A[eqr] @ x, "jac": lambda x: -A[eqr]})
     if inst.proj != "box":
         S = np.zeros((inst.n_users, n))
         for i in range(inst.n_users):
@@ -65,6 +73,34 @@ def test_converged_matches_qp(orc, wl, kw):
     assert np.all(lam >= 0)
     assert grad.max() <= 1e-6
     assert np.abs(lam * grad).max() <= 1e-6
+
+
+def test_equality_rows_free_duals_match_qp(orc, wl):
+    """Equality rows A_1 x = b_1 next to capacity rows A_0 x <= b_0: the duals of
+    the equality family are free (they may be negative); the converged oracle
+    solve matches a generic SQP solve of the primal with the equality
+    constraints, and its gradient on those rows vanishes."""
+    import dataclasses
+    base = wl.random_small(25, 30, 5, 4, n_families=2, a_ones=False, b_scale=0.25)
+    inst = dataclasses.replace(base, eq_families=0b10)
+    # equality targets reachable by construction: b_1 = A_1 x0 for a feasible x0 (half of each row's share)
+    x0 = np.zeros(inst.nnz)
+    for i in range(inst.n_users):
+        s, e = inst.row_ptr[i], inst.row_ptr[i + 1]
+        x0[s:e] = 0.5 / max(e - s, 1)
+    A = dense_A(inst)
+    inst.b[1] = (A[inst.n_items:] @ x0)
+    gamma = 0.1
+    lam, st, _, _ = orc.solve(inst, [gamma], [300_000], max_iters=300_000, check_every=0, jacobi=True)
+    assert np.isnan(st["rel_gap"])
+    g, grad, x, _ = orc.dual_grad(inst, lam, gamma)
+    xq, pq = qp_solve(inst, gamma)
+    np.testing.assert_allclose(x, xq, atol=2e-6)
+    assert abs(g - pq) <= 1e-7 * max(1.0, abs(pq))
+    J = inst.n_items
+    assert np.abs(grad[J:]).max() <= 1e-6           # equality rows hold
+    assert np.all(lam[:J] >= 0) and grad[:J].max() <= 1e-6
+    assert (lam[J:] < 0).any() or (lam[J:] > 0).any()
 
 
 def test_all_slack_literal_capacities(orc, wl):

@@ -155,6 +155,7 @@ class Instance:
     radius: float = 1.0
     meta: dict = field(default_factory=dict)
     upper: float = 0.0   # u of the box-cut set {0 <= x <= u, sum x <= radius}
+    eq_families: int = 0  # bit k: family k holds equality rows A_k x = b_k
 
     @property
     def nnz(self) -> int:
@@ -179,7 +180,7 @@ class Instance:
         a = None if self.a is None else np.ascontiguousarray(self.a[:, s:e])
         return Instance(self.name + f"[{first}:{first + count}]", count, self.n_items, self.n_families,
                         rp, self.item_idx[s:e].copy(), self.c[s:e].copy(), a, self.b.copy(),
-                        self.proj, self.radius, dict(self.meta), self.upper)
+                        self.proj, self.radius, dict(self.meta), self.upper, self.eq_families)
 
 
 def _generate(n_users, n_items, seed, deg_kind, deg_p1, deg_p2, deg_min, deg_max, item_kind,
