@@ -93,6 +93,10 @@ typedef struct {
   int32_t jacobi;           /* 1: Jacobi row scaling in the solver (Appendix C) */
   int32_t wg_per_cu;        /* gradient-pass workgroups per compute unit, 0 = default (4) */
   int32_t layout;           /* dl_layout: user-to-lane mapping of the gradient pass */
+  int32_t eq_families;      /* bit k set: family k holds equality rows A_k x = b_k, whose duals are free
+                               (not clamped at 0); the certificate then has no feasible repair: rel_gap
+                               is NaN, max_slack is max |A x - b| on those rows (give the last stage a
+                               fixed iteration count) */
   void* stream;             /* hipStream_t */
 } dl_problem_desc;
 

@@ -50,6 +50,7 @@ class dl_problem_desc(ctypes.Structure):
         ("jacobi", ctypes.c_int32),
         ("wg_per_cu", ctypes.c_int32),
         ("layout", ctypes.c_int32),
+        ("eq_families", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -217,7 +218,8 @@ class Problem:
     """
 
     def __init__(self, n_users, n_items, n_families, row_ptr, item_idx, c, a, b, proj="simplex_le",
-                 radius=1.0, storage="f32", jacobi=True, wg_per_cu=0, stream=None, layout="bucketed", upper=0.0):
+                 radius=1.0, storage="f32", jacobi=True, wg_per_cu=0, stream=None, layout="bucketed", upper=0.0,
+                 eq_families=0):
         import torch
         self.torch = torch
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -238,7 +240,8 @@ class Problem:
         self.stream = _stream(torch, stream)
         desc = dl_problem_desc(self.I, self.J, self.m, _ptr(self._rp), _ptr(self._idx), _ptr(self._c),
                                _ptr(self._a), bh.ctypes.data, PROJ[proj], STORAGE[storage], float(radius),
-                               float(upper), int(jacobi), int(wg_per_cu), LAYOUT[layout], self.stream)
+                               float(upper), int(jacobi), int(wg_per_cu), LAYOUT[layout], int(eq_families),
+                               self.stream)
         h = ctypes.c_void_p()
         _check(load().dl_problem_create(ctypes.byref(desc), ctypes.byref(h)))
         self.handle = h
@@ -251,7 +254,7 @@ class Problem:
         """From any object with the attributes of a CSR matching instance."""
         return cls(inst.n_users, inst.n_items, inst.n_families, inst.row_ptr, inst.item_idx, inst.c, inst.a,
                    inst.b, inst.proj, inst.radius, storage, jacobi, wg_per_cu, stream, layout,
-                   float(getattr(inst, "upper", 0.0) or 0.0))
+                   float(getattr(inst, "upper", 0.0) or 0.0), int(getattr(inst, "eq_families", 0) or 0))
 
     def close(self):
         if getattr(self, "handle", None):

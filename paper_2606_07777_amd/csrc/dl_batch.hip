@@ -29,6 +29,7 @@ struct bupd {
   int mJ, J;
   int pad;
   const float* qs;  // the instance's fixed-point scales of the pass (device)
+  int eq_mask;      // bit k: family k has free duals
   const double* D;
   const double* b;
   double* lam;
@@ -60,7 +61,8 @@ __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict_
   const double eta = step_scale * gamma / u.lhat;
   const double gs = Dr * (ax - u.b[r]);
   const double lo = u.lam[r];
-  const double ln = fmax(0.0, u.y[r] + eta * gs);
+  const double st = u.y[r] + eta * gs;
+  const double ln = ((u.eq_mask >> (r / u.J)) & 1) ? st : fmax(0.0, st);
   const double yn = ln + beta * (ln - lo);
   u.lam[r] = ln;
   u.y[r] = yn;
@@ -182,6 +184,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     u.mJ = P->m * P->J;
     u.J = P->J;
     u.qs = P->qs_dev;
+    u.eq_mask = P->eq_mask;
     u.D = P->D;
     u.b = P->b;
     u.lam = lam;

@@ -132,6 +132,7 @@ struct dl_problem {
   int32_t J = 0, m = 0, proj = 0, storage = 0, jacobi = 0;
   double radius = 1.0;
   double upper = 0.0;    // u of the box-cut set
+  int32_t eq_mask = 0;   // bit k: family k holds equality rows (free duals)
   int kmax = 16;
   int mf = 1;            // compiled family bound of the kernel variant (1 or 4)
   bool has_a = false;    // at least one stored family

@@ -179,6 +179,7 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   P->storage = d->storage;
   P->radius = d->radius;
   P->upper = d->upper;
+  P->eq_mask = d->eq_families & ((1 << d->n_families) - 1);
   P->jacobi = d->jacobi ? 1 : 0;
   P->stream = (hipStream_t)d->stream;
   DL_HIP_TRY(hipGetDevice(&P->device));
@@ -496,6 +497,7 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** ou
   DL_CHECK_ARG(d->n_families >= 1 && d->n_families <= DL_MAX_FAMILIES, "n_families must be in 1..4");
   DL_CHECK_ARG(d->row_ptr && d->b, "row_ptr and b are required");
   DL_CHECK_ARG(d->proj >= DL_PROJ_SIMPLEX_LE && d->proj <= DL_PROJ_BOXCUT, "unknown projection kind");
+  DL_CHECK_ARG((d->eq_families & ~((1 << d->n_families) - 1)) == 0, "eq_families names a family beyond n_families");
   DL_CHECK_ARG(d->proj != DL_PROJ_BOXCUT || (d->upper > 0.0 && isfinite(d->upper)),
                "box-cut needs a positive, finite upper bound");
   DL_CHECK_ARG(d->storage == DL_F32 || d->storage == DL_BF16, "unknown storage");

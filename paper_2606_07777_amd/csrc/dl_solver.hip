@@ -19,6 +19,7 @@ struct upd_args {
   int n_wg;
   int mJ, J;
   const float* qs;  // fixed-point scale of each family in the pass being reduced (device)
+  int eq_mask;      // bit k: family k has free duals (equality rows)
   const double* D;
   const double* b;
   double* lam;      // scaled lam'
@@ -65,7 +66,8 @@ __global__ void update_kernel(upd_args U) {
   const double Dr = U.D[r];
   const double gs = Dr * (ax - U.b[r]);
   const double lo = U.lam[r];
-  const double ln = fmax(0.0, U.y[r] + U.eta * gs);
+  const double st = U.y[r] + U.eta * gs;
+  const double ln = ((U.eq_mask >> k) & 1) ? st : fmax(0.0, st);
   const double yn = ln + U.beta * (ln - lo);
   U.lam[r] = ln;
   U.y[r] = yn;
@@ -85,11 +87,12 @@ __global__ void reduce_kernel(upd_args U) {
 }
 
 // lam' = max(0, lam0 / D), y' = lam', gather points; or (lam0 == NULL) zeros.
-__global__ void init_state(const double* lam0, const double* D, int mJ, double* lam, double* y, float* mu_y,
-                           float* mu_lam) {
+__global__ void init_state(const double* lam0, const double* D, int mJ, int J, int eq_mask, double* lam, double* y,
+                           float* mu_y, float* mu_lam) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= mJ) return;
-  double l = lam0 ? fmax(0.0, lam0[r] / D[r]) : 0.0;
+  const double l0 = lam0 ? lam0[r] / D[r] : 0.0;
+  double l = ((eq_mask >> (r / J)) & 1) ? l0 : fmax(0.0, l0);
   lam[r] = l;
   y[r] = l;
   float m = (float)(D[r] * l);
@@ -148,8 +151,8 @@ __device__ double block_max(double v, double* sh) {
 //   out[0] = sum_w obj_part[w] - mu.b   (dual value g(mu))
 //   out[1] = max_r (A x - b)_r^+
 //   out[2] = -mu.(A x - b)
-__global__ void cert_items(const double* ax, const double* b, const float* mu, int m, int J, const double* obj_part,
-                           int n_wg, float* rfac, double* out) {
+__global__ void cert_items(const double* ax, const double* b, const float* mu, int m, int J, int eq_mask,
+                           const double* obj_part, int n_wg, float* rfac, double* out) {
   __shared__ double sh[1024];
   double lb = 0.0, slack = 0.0, lg = 0.0;
   for (int j = threadIdx.x; j < J; j += blockDim.x) {
@@ -157,10 +160,11 @@ __global__ void cert_items(const double* ax, const double* b, const float* mu, i
     for (int k = 0; k < m; ++k) {
       const int r = k * J + j;
       const double viol = ax[r] - b[r];
-      slack = fmax(slack, viol);
+      const bool eq = (eq_mask >> k) & 1;
+      slack = fmax(slack, eq ? fabs(viol) : viol);
       lb += (double)mu[r] * b[r];
       lg -= (double)mu[r] * viol;
-      if (ax[r] > b[r]) rj = fmin(rj, b[r] > 0.0 ? b[r] / ax[r] : 0.0);
+      if (!eq && ax[r] > b[r]) rj = fmin(rj, b[r] > 0.0 ? b[r] / ax[r] : 0.0);
     }
     rfac[j] = (float)rj;
   }
@@ -224,6 +228,7 @@ upd_args make_upd(const dl_problem* P) {
   U.mJ = P->m * P->J;
   U.J = P->J;
   U.qs = P->qs_dev;
+  U.eq_mask = P->eq_mask;
   U.D = P->D;
   U.b = P->b;
   return U;
@@ -252,7 +257,7 @@ dl_status certificate(dl_solver* S, dl_solve_stats* st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
   DL_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(cert_items, dim3(1), dim3(1024), 0, P->stream, S->ax, P->b, S->mu_lam, P->m, P->J,
-                     P->obj_part, P->n_wg, P->rfac, P->cert_out);
+                     P->eq_mask, P->obj_part, P->n_wg, P->rfac, P->cert_out);
   DL_HIP_TRY(hipGetLastError());
   DL_TRY(dl_launch_grad(P, M_REPAIR, S->mu_lam, S->gamma, P->rfac, nullptr, nullptr, P->pobj_part));
   hipLaunchKernelGGL(cert_final, dim3(1), dim3(1024), 0, P->stream, P->pobj_part, P->n_wg, P->cert_out);
@@ -265,7 +270,8 @@ dl_status certificate(dl_solver* S, dl_solve_stats* st) {
   st->gamma = S->gamma;
   st->dual_obj = g;
   st->primal_obj = pobj;
-  st->rel_gap = (pobj - g) / fmax(1.0, fabs(g));
+  // equality rows have no feasible repair: the certified gap is undefined
+  st->rel_gap = P->eq_mask ? NAN : (pobj - g) / fmax(1.0, fabs(g));
   st->max_slack = P->cert_host[1];
   st->lagr_gap = P->cert_host[2];
   st->iters = S->iters;
@@ -302,7 +308,7 @@ extern "C" dl_status dl_dual_grad(dl_problem* P, const double* lambda, double ga
   DL_HIP_TRY(hipGetLastError());
   if (want_obj) {
     hipLaunchKernelGGL(cert_items, dim3(1), dim3(1024), 0, P->stream, P->lam_tmp, P->b, P->mu, P->m, P->J,
-                       P->obj_part, P->n_wg, P->rfac, P->cert_out);
+                       P->eq_mask, P->obj_part, P->n_wg, P->rfac, P->cert_out);
     DL_HIP_TRY(hipGetLastError());
     DL_HIP_TRY(hipMemcpyAsync(P->cert_host, P->cert_out, sizeof(double), hipMemcpyDeviceToHost, P->stream));
     DL_HIP_TRY(hipStreamSynchronize(P->stream));
@@ -343,7 +349,8 @@ extern "C" dl_status dl_solver_create(dl_problem* P, const double* lambda0, dl_s
     return fail(DL_ENOMEM);
   }
   if (hipMemsetAsync(S->flag, 0, sizeof(int), P->stream) != hipSuccess) return fail(DL_EHIP);
-  hipLaunchKernelGGL(init_state, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, lambda0, P->D, mJ, S->lam, S->y,
+  hipLaunchKernelGGL(init_state, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, lambda0, P->D, mJ, P->J, P->eq_mask,
+                     S->lam, S->y,
                      S->mu_y, S->mu_lam);
   if (hipGetLastError() != hipSuccess) {
     dl_set_error("init_state launch failed");
@@ -668,12 +675,13 @@ extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const doubl
 // Judged warm start: the candidate with the largest dual value starts the solve
 // ---------------------------------------------------------------------------
 namespace {
-__global__ void project_candidate(const double* in, int n, double* out, int* bad) {
+__global__ void project_candidate(const double* in, int n, int J, int eq_mask, double* out, int* bad) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const double v = in ? in[r] : 0.0;
   if (!isfinite(v)) atomicOr(bad, 1);
-  out[r] = isfinite(v) ? fmax(v, 0.0) : 0.0;
+  const double w = isfinite(v) ? v : 0.0;
+  out[r] = ((eq_mask >> (r / J)) & 1) ? w : fmax(w, 0.0);
 }
 }  // namespace
 
@@ -694,7 +702,8 @@ extern "C" dl_status dl_solve_warm(dl_problem* P, const dl_solve_opts* o, int32_
   dl_status rc = DL_OK;
   for (int q = 0; q < n_cand && rc == DL_OK; ++q) {
     if (hipMemsetAsync(bad, 0, sizeof(int), P->stream) != hipSuccess) { rc = DL_EHIP; break; }
-    hipLaunchKernelGGL(project_candidate, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, cands[q], mJ, tmp, bad);
+    hipLaunchKernelGGL(project_candidate, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, cands[q], mJ, P->J,
+                       P->eq_mask, tmp, bad);
     double g = -INFINITY;
     rc = dl_dual_grad(P, tmp, gamma0, grad, &g, nullptr);
     if (rc != DL_OK) break;
@@ -713,7 +722,8 @@ extern "C" dl_status dl_solve_warm(dl_problem* P, const dl_solve_opts* o, int32_
     rc = DL_NUMERIC;
   }
   if (rc == DL_OK) {
-    hipLaunchKernelGGL(project_candidate, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, cands[best], mJ, tmp, bad);
+    hipLaunchKernelGGL(project_candidate, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, cands[best], mJ, P->J,
+                       P->eq_mask, tmp, bad);
     if (hipGetLastError() != hipSuccess) rc = DL_EHIP;
   }
   dl_status sr = rc;

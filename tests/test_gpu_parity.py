@@ -225,6 +225,33 @@ def test_boxcut_continuation_solve_matches_oracle(dl, orc, wl):
     assert np.isfinite(c["rel_gap"]) and c["rel_gap"] >= -1e-6
 
 
+def test_equality_family_free_duals(dl, orc, wl):
+    """Family 1 as equality rows (free duals) next to capacity rows: the GPU
+    trajectory against the oracle, duals of both signs, NaN certified gap and
+    |Ax - b| slack."""
+    import dataclasses
+    import torch
+    base = wl.random_small(26, 20_000, 200, 30, n_families=2, a_ones=False, b_scale=0.2)
+    inst = dataclasses.replace(base, eq_families=0b10)
+    x0 = np.zeros(inst.nnz)
+    deg = np.diff(inst.row_ptr)
+    x0 = np.repeat(0.97 / np.maximum(deg, 1), deg)  # near-full targets: some rows under-demanded
+    b = inst.b.copy()
+    b[1] = np.bincount(inst.item_idx, weights=inst.a[1].astype(np.float64) * x0, minlength=inst.n_items)
+    inst = dataclasses.replace(inst, b=b)
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    lam, st = prob.solve([1e-1, 1e-2], [200, 200], check_every=0)
+    lo, so, _, _ = orc.solve(inst, [1e-1, 1e-2], [200, 200], jacobi=True, check_every=0)
+    lam = lam.cpu().numpy()
+    rel = np.linalg.norm(lam - lo) / np.linalg.norm(lo)
+    J = inst.n_items
+    print(f"equality family: rel err {rel:.2e}; lam_eq min {lo[J:].min():.3e} max {lo[J:].max():.3e}")
+    assert rel <= 1e-5
+    assert (lo[J:] < 0).any() and (lam[:J] >= 0).all()
+    assert np.isnan(st["rel_gap"]) and np.isnan(so["rel_gap"])
+    assert abs(st["max_slack"] - so["max_slack"]) <= 1e-4 * max(1.0, so["max_slack"])
+
+
 def test_halving_continuation_matches_oracle(dl, orc, wl):
     """The decay of the continuation ablation (gamma 0.16 -> 0.01, halved every
     25 iterations, momentum reset, step scaled with gamma), no Jacobi and with
