@@ -267,6 +267,39 @@ def test_halving_continuation_matches_oracle(dl, orc, wl):
         assert rel <= 1e-5, (jac, rel)
 
 
+@pytest.mark.parametrize("variant", ["two_family_bf16", "stored_a_f32", "boxcut_equality"])
+def test_batch_kernel_variants_match_solo(dl, wl, variant):
+    """The batched kernels of the other variants (four-family kernel with BF16,
+    one stored family, box-cut with an equality family): every member ends
+    bitwise where its solo run ends."""
+    import dataclasses
+    if variant == "two_family_bf16":
+        members = [wl.random_small(300 + k, 3000 + 700 * k, 120, 40, n_families=2, a_ones=False, proj="box")
+                   for k in range(3)]
+        kw = dict(storage="bf16")
+    elif variant == "stored_a_f32":
+        members = [wl.random_small(310 + k, 2500 + 900 * k, 150, 60, a_ones=False) for k in range(3)]
+        kw = {}
+    else:
+        members = []
+        for k in range(3):
+            m = wl.random_small(320 + k, 3000 + 500 * k, 100, 30, n_families=2, proj="boxcut", radius=1.0,
+                                upper=0.4, a_ones=False, b_scale=0.05)
+            deg = np.diff(m.row_ptr)
+            x0 = np.repeat(0.9 / np.maximum(deg, 1), deg)
+            b = m.b.copy()
+            b[1] = np.bincount(m.item_idx, weights=m.a[1].astype(np.float64) * x0, minlength=m.n_items)
+            members.append(dataclasses.replace(m, b=b, eq_families=0b10))
+        kw = {}
+    sched = dict(gammas=[1e-1, 1e-2], iters=[60, 60], check_every=0)
+    probs = [dl.Problem.from_instance(m, jacobi=True, **kw) for m in members]
+    lam_b, st_b = dl.Batch(probs).solve(**sched)
+    for k, p in enumerate(probs):
+        lam_s, st_s = p.solve(**sched)
+        assert st_b[k]["iters"] == st_s["iters"] == 120
+        assert np.array_equal(lam_b[k].cpu().numpy(), lam_s.cpu().numpy()), (variant, k)
+
+
 def test_bitwise_deterministic(dl, cases):
     inst, gamma = cases["production_small"]
     out = []
