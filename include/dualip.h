@@ -251,8 +251,8 @@ dl_status dl_batch_solve(dl_batch* batch, const dl_solve_opts* opts, const doubl
 typedef struct {
   int32_t n_workgroups;     /* gradient-pass grid kept */
   int32_t rounds;           /* balancing rounds per candidate grid */
-  double pass_ms_model;     /* mean pass time, cost-model split, at the kept grid */
-  double pass_ms_tuned;     /* mean pass time after balancing */
+  double pass_ms_model;     /* mean pass + partial-sum reduction time, cost-model split, at the kept grid */
+  double pass_ms_tuned;     /* the same after balancing (10 passes, the time the grid was chosen on) */
   double imbalance_model;   /* max / mean workgroup time before balancing */
   double imbalance_tuned;   /* the same after */
 } dl_tune_result;

@@ -488,6 +488,10 @@ namespace {
 
 // Runs `reps` histogram passes at the solver's point with workgroup clocks on;
 // returns the mean pass time and the last pass's per-workgroup durations.
+// Mean time of reps gradient passes, each followed by the reduction of its
+// partial sums (the part of an iteration the split decides), and the per-
+// workgroup durations of the last pass.  The reduced sums are discarded, so
+// the solver state is unchanged.
 dl_status measure_pass(dl_solver* S, int reps, double* ms, std::vector<double>* dur) {
   dl_problem* P = S->P;
   hipEvent_t e0, e1;
@@ -496,10 +500,15 @@ dl_status measure_pass(dl_solver* S, int reps, double* ms, std::vector<double>* 
   P->clocking = true;
   dl_status rc = DL_OK;
   if (hipEventRecord(e0, P->stream) != hipSuccess) rc = DL_EHIP;
-  for (int r = 0; r < reps && rc == DL_OK; ++r)
+  for (int r = 0; r < reps && rc == DL_OK; ++r) {
     rc = dl_launch_grad(P, M_HIST, S->mu_y, S->gamma, nullptr, nullptr, nullptr, nullptr);
+    if (rc == DL_OK) rc = launch_reduce(P);
+  }
   P->clocking = false;
   if (rc == DL_OK && hipEventRecord(e1, P->stream) != hipSuccess) rc = DL_EHIP;
+  if (rc == DL_OK &&
+      hipMemsetAsync(P->acc, 0, sizeof(unsigned long long) * (size_t)P->m * P->J, P->stream) != hipSuccess)
+    rc = DL_EHIP;
   std::vector<unsigned long long> clk(2 * (size_t)std::max(P->n_wg, 1));
   if (rc == DL_OK && P->n_wg > 0 &&
       hipMemcpyAsync(clk.data(), P->wg_clock, sizeof(unsigned long long) * 2 * P->n_wg, hipMemcpyDeviceToHost,
@@ -558,9 +567,16 @@ extern "C" dl_status dl_solver_autotune(dl_solver* S, int32_t rounds, dl_tune_re
   memset(out, 0, sizeof(*out));
   out->rounds = rounds;
   if (P->n_tasks == 0) return DL_OK;
-  const int reps = 3;
-  double best_ms = 1e300;
-  std::vector<int64_t> best;
+  const int reps = 3, final_reps = 10;
+  // per grid size: the best split found by the balancing rounds; the finalists
+  // are timed again with more passes before one is kept (a minimum over short,
+  // noisy timings would favour whichever candidate happened to run fastest)
+  struct cand {
+    int nw;
+    std::vector<int64_t> b;
+    double ms_model, imb_model, imb;
+  };
+  std::vector<cand> cands;
   for (int k = 1;; k *= 2) {
     int nw = (int)std::min<int64_t>((int64_t)P->n_cu * k, (P->n_tasks + DL_WAVES - 1) / DL_WAVES);
     nw = std::max(1, std::min(nw, P->n_wg_cap));
@@ -583,18 +599,28 @@ extern "C" dl_status dl_solver_autotune(dl_solver* S, int32_t rounds, dl_tune_re
         cur = nb;
       }
     }
-    if (cur_ms < best_ms) {
-      best_ms = cur_ms;
-      best = cur;
-      out->n_workgroups = nw;
-      out->pass_ms_model = ms_model;
-      out->imbalance_model = imb_model;
-      out->pass_ms_tuned = cur_ms;
-      out->imbalance_tuned = cur_imb;
-    }
+    cands.push_back({nw, cur, ms_model, imb_model, cur_imb});
     if (nw >= P->n_wg_cap || (int64_t)P->n_cu * k * 2 > P->n_wg_cap) break;
   }
-  return dl_set_partition(P, best);
+  double best_ms = 1e300;
+  size_t best = 0;
+  for (size_t q = 0; q < cands.size(); ++q) {
+    DL_TRY(dl_set_partition(P, cands[q].b));
+    double ms;
+    std::vector<double> dur;
+    DL_TRY(measure_pass(S, final_reps, &ms, &dur));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = q;
+    }
+  }
+  const cand& c = cands[best];
+  out->n_workgroups = c.nw;
+  out->pass_ms_model = c.ms_model;
+  out->imbalance_model = c.imb_model;
+  out->pass_ms_tuned = best_ms;
+  out->imbalance_tuned = c.imb;
+  return dl_set_partition(P, c.b);
 }
 
 extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const double* lambda0, double* lambda_out,
