@@ -183,8 +183,10 @@ struct dl_problem {
 };
 
 // Gradient pass and projection launches (dl_grad.hip).
+// A histogram pass first sets its fixed-point scales (dl_launch_qscale) unless
+// the caller has just done so for the same mu and gamma (scaled = true).
 dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double gamma,
-                         const float* rfac, const float* v_in, float* x_out, double* obj_part);
+                         const float* rfac, const float* v_in, float* x_out, double* obj_part, bool scaled = false);
 size_t dl_grad_lds_bytes(const dl_problem* P, int mode);
 dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamma);
 // Task ranges of n_wg workgroups with equal cost-model weight.

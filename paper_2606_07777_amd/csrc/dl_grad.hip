@@ -962,10 +962,10 @@ dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamm
 }
 
 dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double gamma, const float* rfac,
-                         const float* v_in, float* x_out, double* obj_part) {
+                         const float* v_in, float* x_out, double* obj_part, bool scaled) {
   if (P->n_wg <= 0) return DL_OK;
   if (x_out) mode |= M_XOUT;
-  if (mode & M_HIST) DL_TRY(dl_launch_qscale(P, mu, gamma));
+  if ((mode & M_HIST) && !scaled) DL_TRY(dl_launch_qscale(P, mu, gamma));
   dl_grad_args A = dl_make_grad_args(P, mu, gamma);
   A.rfac = rfac;
   A.v_in = v_in;

@@ -417,11 +417,13 @@ extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
   U.flag = S->flag;
   for (int64_t it = 0; it < n; ++it) {
     std::pair<hipEvent_t, hipEvent_t>* eg = nullptr;
+    // the pass's fixed-point scales first, so the timing events bracket the gradient kernel alone
+    DL_TRY(dl_launch_qscale(P, S->mu_y, S->gamma));
     if (S->timing) {
       DL_TRY(next_event_pair(S->ev_grad, S->n_ev_grad, &eg));
       DL_HIP_TRY(hipEventRecord(eg->first, P->stream));
     }
-    DL_TRY(dl_launch_grad(P, M_HIST, S->mu_y, S->gamma, nullptr, nullptr, nullptr, nullptr));
+    DL_TRY(dl_launch_grad(P, M_HIST, S->mu_y, S->gamma, nullptr, nullptr, nullptr, nullptr, true));
     std::pair<hipEvent_t, hipEvent_t>* eu = nullptr;
     if (S->timing) {
       DL_HIP_TRY(hipEventRecord(eg->second, P->stream));
