@@ -178,6 +178,7 @@ struct dl_problem {
   float* rfac = nullptr;               // J
   double* lam_tmp = nullptr;           // m*J
   double* cert_out = nullptr;          // 8 doubles
+  int* upd_flag = nullptr;             // dl_problem_update's non-finite flag
   double* cert_host = nullptr;         // pinned, 8 doubles
   double device_bytes = 0;
 };

@@ -162,7 +162,8 @@ dl_status dmalloc(dl_problem* P, T** p, size_t n) {
 void free_problem(dl_problem* P) {
   if (!P) return;
   void* ptrs[] = {P->rp, P->idx, P->cval, P->aval, P->orig_rp, P->wg_task, P->wg_clock, P->b, P->D, P->part, P->acc,
-                  P->obj_part, P->pobj_part, P->mu, P->rfac, P->lam_tmp, P->cert_out, P->ext, P->qs_dev};
+                  P->obj_part, P->pobj_part, P->mu, P->rfac, P->lam_tmp, P->cert_out, P->ext, P->qs_dev,
+                  P->upd_flag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->cert_host) (void)hipHostFree(P->cert_host);
@@ -441,6 +442,7 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   DL_TRY(dmalloc(P, &P->cert_out, 16));
   DL_HIP_TRY(hipHostMalloc((void**)&P->cert_host, sizeof(double) * 16, hipHostMallocDefault));
   DL_TRY(dmalloc(P, &P->qs_dev, (size_t)DL_MAX_FAMILIES));
+  DL_TRY(dmalloc(P, &P->upd_flag, 1));
   DL_HIP_TRY(hipMemcpyAsync(P->qs_dev, P->qscale, sizeof(float) * DL_MAX_FAMILIES, hipMemcpyHostToDevice, st));
   DL_TRY(dmalloc(P, &P->ext, (size_t)J * (size_t)(2 + 2 * P->n_stored)));
   DL_TRY(dl_item_extremes(P, false));
@@ -561,7 +563,7 @@ extern "C" dl_status dl_problem_update(dl_problem* P, const float* c, const doub
   if (b)
     for (int64_t r = 0; r < mJ; ++r) DL_CHECK_ARG(isfinite(b[r]), "b has a non-finite entry");
   if (c && P->nnz > 0) {
-    int* flag = reinterpret_cast<int*>(P->cert_out);  // scratch int, not in use between calls
+    int* flag = P->upd_flag;
     DL_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
     const int64_t threads = P->I * 64;
     hipLaunchKernelGGL(regather_c, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, P->orig_rp, P->rp, P->I,
