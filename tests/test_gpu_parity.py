@@ -300,6 +300,25 @@ def test_batch_kernel_variants_match_solo(dl, wl, variant):
         assert np.array_equal(lam_b[k].cpu().numpy(), lam_s.cpu().numpy()), (variant, k)
 
 
+@pytest.mark.parametrize("name,jacobi", [("tiny_plain_binding", False), ("production_small", True)])
+def test_bf16_trajectory_within_1e3_of_fp64(dl, orc, cases, name, jacobi):
+    """BF16 storage against the FP64 oracle on the original (unrounded) data:
+    lam after 200 iterations within 1e-3 relative.  Rounding the data alone moves
+    lam by 6.7e-4 (tiny binding) and 1.2e-4 (production shape) on these inputs;
+    the two-family instance with lognormal a is covered by the rounded-data
+    comparison instead (its data distance is 1.3e-3)."""
+    inst, gamma = cases[name]
+    prob = dl.Problem.from_instance(inst, storage="bf16", jacobi=jacobi)
+    s = prob.solver()
+    s.set_stage(gamma, 1.0, True)
+    s.step(200)
+    lam = s.lam().cpu().numpy()
+    lo, _, _, _ = orc.solve(inst, [gamma], [200], jacobi=jacobi, check_every=0)
+    rel = np.linalg.norm(lam - lo) / np.linalg.norm(lo)
+    print(f"{name}: BF16 lam vs FP64 oracle on the original data: {rel:.2e}")
+    assert rel <= 1e-3
+
+
 def test_bitwise_deterministic(dl, cases):
     inst, gamma = cases["production_small"]
     out = []
