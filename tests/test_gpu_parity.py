@@ -139,6 +139,25 @@ def test_trajectory_tiny_plain_binding(dl, orc, cases):
         assert rel <= 1e-5, (k, rel)
 
 
+def test_trajectory_production_prefix(dl, orc, cases):
+    """The production shape (Zipf items, lognormal degrees, Jacobi) over the start
+    of its continuation schedule: lam after 50 iterations at gamma 0.1 and 50
+    more at 0.01 within 1e-5 of the FP64 oracle."""
+    inst, _ = cases["production_small"]
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    s = prob.solver()
+    out = []
+    for g in (1e-1, 1e-2):
+        s.set_stage(g, 1.0, True)
+        s.step(50)
+        out.append(s.lam().cpu().numpy())
+    _, _, snaps, _ = orc.solve(inst, [1e-1, 1e-2], [50, 50], jacobi=True, check_every=0, snap_iters=[50, 100])
+    for k, (lg, lo) in enumerate(zip(out, snaps)):
+        rel = np.linalg.norm(lg - lo) / np.linalg.norm(lo)
+        print(f"production prefix, iteration {50 * (k + 1)}: rel lam err {rel:.3e}")
+        assert rel <= 1e-5
+
+
 def test_literal_capacities_stay_slack(dl, orc, wl):
     import torch
     inst = wl.tiny_plain(seed=0, binding=False)
