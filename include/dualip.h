@@ -5,9 +5,11 @@
  * Problem (paper eq. 1):  min_{x in C} c^T x + (gamma/2)||x||^2  s.t.  A x <= b
  *   x        one variable per eligible (user i, item j) pair, user-major
  *   C        product of per-user sets: simplex {x_i >= 0, sum x_i <= z},
- *            simplex {x_i >= 0, sum x_i = z}, or box [0,u]^(d_i) (Section 3.3)
+ *            simplex {x_i >= 0, sum x_i = z}, box [0,u]^(d_i) (Section 3.3), or
+ *            box-cut {0 <= x_i <= u, sum x_i <= z} (Table 1's third kind)
  *   A        m coupling families; family k has one row per item j and
- *            A[(k,j),(i,j)] = a_kij (Definition 1: diagonal per-user blocks)
+ *            A[(k,j),(i,j)] = a_kij (Definition 1: diagonal per-user blocks);
+ *            a family may hold equality rows A_k x = b_k (free duals)
  * Dual (eq. 2): g(lam) = min_{x in C} c^T x + (gamma/2)||x||^2 + lam^T (A x - b)
  * Primal recovery (eq. 3): x*(lam) = Pi_C(-(A^T lam + c)/gamma)
  * Gradient (eq. 4): grad g(lam) = A x*(lam) - b
@@ -16,6 +18,9 @@
  *   ObjectiveFunction.calculate -> dl_dual_grad
  *   ProjectionMap               -> dl_project
  *   Maximizer                   -> dl_solve (and the stepwise dl_solver_*)
+ * Beyond them: dl_batch_* (many problems per launch), dl_problem_update and
+ * dl_solve_warm (recurring solves), dl_item_features and dl_mlp_* (learned
+ * warm start).
  *
  * Conventions shared by every entry point
  *   Memory    Arrays marked "device" are caller-owned device pointers on the
