@@ -211,6 +211,25 @@ dl_status dl_solver_set_stage(dl_solver* s, double gamma, double step_scale, int
 dl_status dl_solver_step(dl_solver* s, int64_t n);
 /* Current lam (device, m*J). */
 dl_status dl_solver_get_lambda(dl_solver* s, double* lambda_out);
+
+/*
+ * Checkpoint / resume of a stepwise solve.  dl_solver_export copies the dual
+ * state into state (device, 2*m*J: the Jacobi-scaled lam' then the momentum
+ * point y', in the solver's internal units: opaque) and fills meta (host).
+ * dl_solver_import loads both into a solver of a problem with the same data
+ * (same layout, scaling and step bound); the next dl_solver_step continues
+ * bitwise where the exported solver stood.  DL_EINVAL on a size mismatch or
+ * an invalid meta.  Neither call synchronises.
+ */
+typedef struct {
+  double gamma;       /* current stage's gamma */
+  double eta;         /* current step */
+  double tk;          /* FISTA momentum sequence t_k (>= 1) */
+  int64_t iters;      /* iterations taken */
+  int64_t m_times_j;  /* size check: m*J of the exporting problem */
+} dl_solver_meta;
+dl_status dl_solver_export(dl_solver* s, double* state, dl_solver_meta* meta);
+dl_status dl_solver_import(dl_solver* s, const double* state, const dl_solver_meta* meta);
 /* Certificate at the current lam and gamma (synchronises). */
 dl_status dl_solver_certificate(dl_solver* s, dl_solve_stats* out);
 

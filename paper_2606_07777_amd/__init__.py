@@ -55,6 +55,16 @@ class dl_problem_desc(ctypes.Structure):
     ]
 
 
+class dl_solver_meta(ctypes.Structure):
+    _fields_ = [
+        ("gamma", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("tk", ctypes.c_double),
+        ("iters", ctypes.c_int64),
+        ("m_times_j", ctypes.c_int64),
+    ]
+
+
 class dl_problem_info(ctypes.Structure):
     _fields_ = [
         ("n_users", ctypes.c_int64),
@@ -160,6 +170,8 @@ SIGNATURES = {
     "dl_batch_solve": ([_VP, ctypes.POINTER(dl_solve_opts), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                         ctypes.POINTER(dl_solve_stats)], _I32),
     "dl_item_features": ([_VP, _VP, _VP, _VP, _VP], _I32),
+    "dl_solver_export": ([_VP, _VP, ctypes.POINTER(dl_solver_meta)], _I32),
+    "dl_solver_import": ([_VP, _VP, ctypes.POINTER(dl_solver_meta)], _I32),
     "dl_mlp_set_input_norm": ([_VP, _VP, _VP], _I32),
     "dl_mlp_predict_duals": ([_VP, _VP, _I64, _VP, ctypes.c_double, _VP], _I32),
     "dl_problem_update": ([_VP, _VP, _VP], _I32),
@@ -395,6 +407,23 @@ class Solver:
         out = self.prob._empty(self.prob.m * self.prob.J, self.prob.torch.float64)
         _check(load().dl_solver_get_lambda(self.handle, _ptr(out)))
         return out
+
+    def export_state(self):
+        """(state tensor on the device, meta dict): a checkpoint of the dual state."""
+        torch = self.prob.torch
+        state = self.prob._empty(2 * self.prob.m * self.prob.J, torch.float64)
+        meta = dl_solver_meta()
+        _check(load().dl_solver_export(self.handle, _ptr(state), ctypes.byref(meta)))
+        return state, {f: getattr(meta, f) for f, _ in meta._fields_}
+
+    def import_state(self, state, meta: dict):
+        """Loads a checkpoint from export_state (same problem data)."""
+        torch = self.prob.torch
+        state = state.to(device="cuda", dtype=torch.float64).contiguous()
+        if state.numel() != 2 * self.prob.m * self.prob.J:
+            raise ValueError("state size does not match the problem")
+        m = dl_solver_meta(**meta)
+        _check(load().dl_solver_import(self.handle, _ptr(state), ctypes.byref(m)))
 
     def certificate(self) -> dict:
         st = dl_solve_stats()

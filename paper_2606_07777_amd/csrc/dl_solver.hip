@@ -443,6 +443,52 @@ extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
   return DL_OK;
 }
 
+// Checkpoint / resume: the scaled dual state (lam', y') is copied as is, so a
+// resumed run continues bitwise where the exported one stood.
+namespace {
+__global__ void state_gather_points(const double* D, int mJ, const double* lam, const double* y, float* mu_y,
+                                    float* mu_lam) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mJ) return;
+  mu_y[r] = (float)(D[r] * y[r]);
+  mu_lam[r] = (float)(D[r] * lam[r]);
+}
+}  // namespace
+
+extern "C" dl_status dl_solver_export(dl_solver* S, double* state, dl_solver_meta* meta) {
+  DL_CHECK_ARG(S && state && meta, "NULL argument");
+  dl_problem* P = S->P;
+  const size_t mJ = (size_t)P->m * P->J;
+  DL_HIP_TRY(hipMemcpyAsync(state, S->lam, sizeof(double) * mJ, hipMemcpyDeviceToDevice, P->stream));
+  DL_HIP_TRY(hipMemcpyAsync(state + mJ, S->y, sizeof(double) * mJ, hipMemcpyDeviceToDevice, P->stream));
+  meta->gamma = S->gamma;
+  meta->eta = S->eta;
+  meta->tk = S->tk;
+  meta->iters = S->iters;
+  meta->m_times_j = (int64_t)mJ;
+  return DL_OK;
+}
+
+extern "C" dl_status dl_solver_import(dl_solver* S, const double* state, const dl_solver_meta* meta) {
+  DL_CHECK_ARG(S && state && meta, "NULL argument");
+  dl_problem* P = S->P;
+  const int mJ = P->m * P->J;
+  DL_CHECK_ARG(meta->m_times_j == mJ, "state was exported from a problem of another size");
+  DL_CHECK_ARG(meta->gamma > 0.0 && isfinite(meta->gamma) && meta->eta > 0.0 && isfinite(meta->eta) &&
+                   meta->tk >= 1.0 && isfinite(meta->tk) && meta->iters >= 0,
+               "invalid solver state");
+  DL_HIP_TRY(hipMemcpyAsync(S->lam, state, sizeof(double) * mJ, hipMemcpyDeviceToDevice, P->stream));
+  DL_HIP_TRY(hipMemcpyAsync(S->y, state + mJ, sizeof(double) * mJ, hipMemcpyDeviceToDevice, P->stream));
+  hipLaunchKernelGGL(state_gather_points, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, P->D, mJ, S->lam, S->y,
+                     S->mu_y, S->mu_lam);
+  DL_HIP_TRY(hipGetLastError());
+  S->gamma = meta->gamma;
+  S->eta = meta->eta;
+  S->tk = meta->tk;
+  S->iters = meta->iters;
+  return DL_OK;
+}
+
 extern "C" dl_status dl_solver_get_lambda(dl_solver* S, double* out) {
   DL_CHECK_ARG(S && out, "NULL argument");
   dl_problem* P = S->P;

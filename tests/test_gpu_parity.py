@@ -338,6 +338,33 @@ def test_bf16_trajectory_within_1e3_of_fp64(dl, orc, cases, name, jacobi):
     assert rel <= 1e-3
 
 
+def test_checkpoint_resume_is_bitwise(dl, cases):
+    """Export after 70 iterations, resume in a fresh solver on a fresh problem of
+    the same data, continue; equals the uninterrupted run bitwise (also across a
+    stage switch after the resume)."""
+    inst, gamma = cases["production_small"]
+    p1 = dl.Problem.from_instance(inst, jacobi=True)
+    a = p1.solver()
+    a.set_stage(1e-1, 1.0, True)
+    a.step(70)
+    state, meta = a.export_state()
+    state = state.clone()
+    a.step(30)
+    a.set_stage(1e-2, 1.0, True)
+    a.step(40)
+    ref = a.lam().cpu().numpy()
+    p2 = dl.Problem.from_instance(inst, jacobi=True)
+    b = p2.solver()
+    b.import_state(state, meta)
+    b.step(30)
+    b.set_stage(1e-2, 1.0, True)
+    b.step(40)
+    assert np.array_equal(b.lam().cpu().numpy(), ref)
+    bad = dict(meta, m_times_j=meta["m_times_j"] + 1)
+    with pytest.raises(RuntimeError):
+        b.import_state(state, bad)
+
+
 def test_bitwise_deterministic(dl, cases):
     inst, gamma = cases["production_small"]
     out = []
