@@ -234,9 +234,10 @@ def batch_bench(args):
     """The uneven batch: 64 instances (users log-uniform in [5e4, 2e6], items
     log-uniform in [100, 5000], degree round(lognormal(3.5, 0.8)), uniform items,
     c = -U(0,1), a = 1, binding b = 0.5 I/J, simplex <= 1) solved to a 1e-4 gap
-    (gamma 1e-1, 1e-2 for 300 iterations each, then 1e-3), once as one batch
-    (one launch per iteration phase for all live members) and once as 64
-    sequential solo solves.  Prints its own JSON line."""
+    (gamma 1e-1, 1e-2 for 300 iterations each, then 1e-3): as one batch (one
+    launch per iteration phase for all live members) with the tuned workgroup
+    split, again with the cost-model split, and as 64 sequential solo solves.
+    Prints its own JSON line."""
     import numpy as np
     import torch
 
@@ -252,11 +253,23 @@ def batch_bench(args):
     sched = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[300, 300, -1], tol=1e-4, max_iters=20000, check_every=10)
     batch = dl.Batch(probs)
     torch.cuda.synchronize()
+    tune = None
+    if args.batch_tune > 0:
+        # the tuned solve runs first, so any first-launch cost falls on it
+        t0 = time.perf_counter()
+        lam_b, st_b = batch.solve(autotune=args.batch_tune, **sched)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        tune = batch.tune()
+        log(f"batch, tuned split: {t_batch:.2f}s; tuner {tune}")
     t0 = time.perf_counter()
-    lam_b, st_b = batch.solve(**sched)
+    lam_u, st_u = batch.solve(**sched)
     torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    log(f"batch: {t_batch:.2f}s, iterations {min(s['iters'] for s in st_b)}..{max(s['iters'] for s in st_b)}")
+    t_untuned = time.perf_counter() - t0
+    log(f"batch, cost-model split: {t_untuned:.2f}s, "
+        f"iterations {min(s['iters'] for s in st_u)}..{max(s['iters'] for s in st_u)}")
+    if args.batch_tune <= 0:
+        lam_b, st_b, t_batch = lam_u, st_u, t_untuned
     t0 = time.perf_counter()
     st_s = []
     for p in probs:
@@ -266,9 +279,10 @@ def batch_bench(args):
     log(f"solo: {t_solo:.2f}s")
     work_b = sum(n * s["iters"] for n, s in zip(nnz, st_b))
     work_s = sum(n * s["iters"] for n, s in zip(nnz, st_s))
-    same = all(a["iters"] == b["iters"] for a, b in zip(st_b, st_s))
+    same = all(a["iters"] == b["iters"] == c["iters"] for a, b, c in zip(st_b, st_s, st_u))
     out = {"metric": "time to a 1e-4 gap for every member of the uneven batch", "unit": "s",
-           "batch_s": t_batch, "solo_sequential_s": t_solo, "speedup": t_solo / t_batch,
+           "batch_s": t_batch, "batch_cost_model_split_s": t_untuned, "batch_tuner": tune,
+           "solo_sequential_s": t_solo, "speedup": t_solo / t_batch,
            "batch_nnz_iter_per_s": work_b / t_batch, "solo_nnz_iter_per_s": work_s / t_solo,
            "same_iterations_as_solo": same, "members": len(members), "nnz": int(sum(nnz)),
            "converged": int(sum(s["status"] == 0 for s in st_b)),
@@ -291,6 +305,8 @@ def main():
                     help="also run the six-stage gamma schedule 1e3..1e-2 with this many iterations per stage")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--batch-tune", type=int, default=2,
+                    help="balancing rounds of the batch tuner (0: cost-model split only)")
     ap.add_argument("--users", type=int, default=10_000_000)
     ap.add_argument("--items", type=int, default=10_000)
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16"])

@@ -174,7 +174,8 @@ typedef struct {
   double tol;              /* stop when the certified relative gap <= tol (final stage) */
   int64_t max_iters;       /* total iteration cap */
   int32_t reset_momentum;  /* 1: restart the momentum at each stage switch */
-  int32_t autotune_rounds; /* > 0: dl_solver_autotune once, after up to 50 iterations of stage 0 */
+  int32_t autotune_rounds; /* > 0: dl_solver_autotune once, after up to 50 iterations of stage 0
+                              (dl_batch_solve: the batch's own tuner, at the same point) */
   double step_scale;       /* step = step_scale * gamma / lhat */
 } dl_solve_opts;
 
@@ -260,6 +261,13 @@ void dl_batch_destroy(dl_batch* batch); /* NULL-safe; does not destroy the probl
  * iteration is one gradient-pass launch over all live members (workgroups
  * dealt by pass cost) plus one update launch.  Members leave the launch when
  * their certified gap reaches tol at a check point of the final stage.
+ * With opts->autotune_rounds > 0 the pass cost is measured once, after up to
+ * 50 iterations of the first stage: the batched pass is timed with per-
+ * workgroup clock stamps and the workgroups are re-dealt (between members and
+ * inside each) from the measured times that many times; the faster of the
+ * best re-dealt split and the cost-model split is kept for the rest of the
+ * solve (dl_batch_get_tune reports it).  The split never changes a member's
+ * iterates: they stay bitwise equal to its solo solve.
  *   lambda0     host array of n device pointers (m_i*J_i each), or NULL (zeros)
  *   lambda_out  host array of n device pointers (m_i*J_i each)
  *   stats       host array of n records (iters and status per member)
@@ -291,6 +299,13 @@ typedef struct {
  * solver's iterate.  Synchronises the stream.
  */
 dl_status dl_solver_autotune(dl_solver* s, int32_t rounds, dl_tune_result* out);
+/*
+ * The tuning of the last dl_batch_solve run on this batch (all zeros when it
+ * ran without autotune_rounds).  Here pass_ms_* is the mean time of one
+ * batched gradient pass with its fixed-point scale pass (10 passes each), and
+ * n_workgroups the grid of the kept split over the members live when tuned.
+ */
+dl_status dl_batch_get_tune(const dl_batch* batch, dl_tune_result* out);
 
 /* ----------------------------------------------------------------------- */
 /* Learned warm start (not part of the paper's method).                    */

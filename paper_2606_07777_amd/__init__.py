@@ -169,6 +169,7 @@ SIGNATURES = {
     "dl_batch_destroy": ([_VP], None),
     "dl_batch_solve": ([_VP, ctypes.POINTER(dl_solve_opts), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                         ctypes.POINTER(dl_solve_stats)], _I32),
+    "dl_batch_get_tune": ([_VP, ctypes.POINTER(dl_tune_result)], _I32),
     "dl_item_features": ([_VP, _VP, _VP, _VP, _VP], _I32),
     "dl_solver_export": ([_VP, _VP, ctypes.POINTER(dl_solver_meta)], _I32),
     "dl_solver_import": ([_VP, _VP, ctypes.POINTER(dl_solver_meta)], _I32),
@@ -467,14 +468,15 @@ class Batch:
             pass
 
     def solve(self, gammas, iters, tol=1e-4, max_iters=20000, check_every=10, reset_momentum=True,
-              step_scale=1.0, lam0=None):
-        """Returns ([lam tensor per member], [stats dict per member])."""
+              step_scale=1.0, lam0=None, autotune=0):
+        """Returns ([lam tensor per member], [stats dict per member]).  autotune > 0
+        re-deals the workgroups from measured time that many rounds (see tune())."""
         torch = self.probs[0].torch
         n = len(self.probs)
         g = np.ascontiguousarray(gammas, dtype=np.float64)
         it = np.ascontiguousarray(iters, dtype=np.int64)
         o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
-                          int(reset_momentum), 0, float(step_scale))
+                          int(reset_momentum), int(autotune), float(step_scale))
         outs = [p._empty(p.m * p.J, torch.float64) for p in self.probs]
         out_arr = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
         l0 = None
@@ -485,6 +487,12 @@ class Batch:
         _check(load().dl_batch_solve(self.handle, ctypes.byref(o), l0, out_arr, stats),
                allow=(DL_OK, DL_NOT_CONVERGED))
         return outs, [s.as_dict() for s in stats]
+
+    def tune(self):
+        """dl_batch_get_tune: the last solve's workgroup tuning as a dict."""
+        r = dl_tune_result()
+        _check(load().dl_batch_get_tune(self.handle, ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in dl_tune_result._fields_}
 
 
 class MLP:

@@ -3,10 +3,13 @@
 //
 // Workgroups are dealt to instances in proportion to their pass cost (several
 // per compute unit, so the hardware's workgroup dispatch evens out what the
-// static split leaves uneven).  Each workgroup serves a contiguous task range
-// of one instance and writes its integer histogram into that instance's own
-// partial slots, so every instance's gradient is bitwise the one its solo pass
-// gives.  All instances follow the same gamma schedule in lockstep; the
+// static split leaves uneven).  The cost is the problem's own per-task model
+// until the tuner has timed the batched pass; from then on it is the measured
+// time of every workgroup's range, spread over the range's tasks by the model.
+// Each workgroup serves a contiguous task range of one instance and writes its
+// integer histogram into that instance's own partial slots, so every
+// instance's gradient is bitwise the one its solo pass gives, whatever the
+// split.  All instances follow the same gamma schedule in lockstep; the
 // certificate runs per instance at the check points of the final stage, and
 // converged instances leave the launch tables.
 #include <math.h>
@@ -71,6 +74,13 @@ __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict_
   if (!isfinite(ln) || !isfinite(yn)) atomicOr(u.flag, 1);
 }
 
+// Measured cost of one instance's pass: workgroup ranges [b[k], b[k+1]) and
+// the clock ticks each took.  Empty = not measured.
+struct inst_profile {
+  std::vector<int64_t> b;
+  std::vector<double> ticks;
+};
+
 }  // namespace
 
 struct dl_batch {
@@ -94,26 +104,86 @@ struct dl_batch {
   std::vector<dl_wg_desc> h_wgs;
   std::vector<bupd> h_upd;
   std::vector<bblk> h_blk;
+  std::vector<int> live;           // the instances the tables were built for
+  std::vector<size_t> wg_first;    // per live position: its first workgroup in h_wgs
+  // per-workgroup (start, end) clock stamps of a timed pass, 2 * clock_cap
+  unsigned long long* d_clock = nullptr;
+  size_t clock_cap = 0;
+  std::vector<double> model_tot;   // per instance: total cost-model weight of its tasks
+  std::vector<inst_profile> prof;  // per instance: measured cost profile (empty: cost model)
+  dl_tune_result tune;             // last tuning result (zeros before any)
 };
 
 static void free_batch(dl_batch* B) {
   if (!B) return;
   for (dl_solver* s : B->solvers) dl_solver_destroy(s);
-  void* ptrs[] = {B->d_args, B->d_wgs, B->d_upd, B->d_blk, B->d_part};
+  void* ptrs[] = {B->d_args, B->d_wgs, B->d_upd, B->d_blk, B->d_part, B->d_clock};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete B;
+}
+
+// Task boundaries of w workgroups over one instance with equal estimated time.
+// A task weighs its cost-model weight; inside each measured range the weights
+// are scaled so that the range adds up to its measured time.
+static std::vector<int64_t> split_tasks(const dl_problem* P, int w, const inst_profile& pr) {
+  const int64_t T = P->n_tasks;
+  std::vector<double> f;  // per measured range: ticks per unit of model weight
+  if (!pr.ticks.empty()) {
+    f.resize(pr.ticks.size());
+    for (size_t k = 0; k < pr.ticks.size(); ++k) {
+      double mc = 0.0;
+      for (int64_t t = pr.b[k]; t < pr.b[k + 1]; ++t) mc += P->task_cost[(size_t)t];
+      f[k] = mc > 0.0 ? std::max(pr.ticks[k], 1.0) / mc : 0.0;
+    }
+  }
+  std::vector<double> wt((size_t)T);
+  double tot = 0.0;
+  size_t k = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    double c = P->task_cost[(size_t)t];
+    if (!f.empty()) {
+      while (k + 1 < f.size() && t >= pr.b[k + 1]) ++k;
+      c *= f[k];
+    }
+    wt[(size_t)t] = c;
+    tot += c;
+  }
+  std::vector<int64_t> bounds((size_t)w + 1, 0);
+  double run = 0.0;
+  int64_t t = 0;
+  for (int q = 1; q < w; ++q) {
+    const double target = tot * (double)q / (double)w;
+    while (t < T && run + 0.5 * wt[(size_t)t] < target) run += wt[(size_t)t++];
+    bounds[(size_t)q] = t;
+  }
+  bounds[(size_t)w] = T;
+  return bounds;
 }
 
 // Rebuilds the launch tables for the live instances at gamma.
 static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double gamma) {
   // earlier launches may still read the tables about to be replaced
   DL_HIP_TRY(hipStreamSynchronize(B->stream));
+  // pass cost per instance: measured ticks where profiled, else the cost model
+  // in the ticks-per-weight ratio of the profiled ones
+  double meas = 0.0, meas_model = 0.0;
+  for (int i : live)
+    if (!B->prof[i].ticks.empty()) {
+      for (double v : B->prof[i].ticks) meas += std::max(v, 1.0);
+      meas_model += B->model_tot[i];
+    }
+  const double ratio = (meas > 0.0 && meas_model > 0.0) ? meas / meas_model : 1.0;
   std::vector<double> cost(live.size());
   double tot = 0.0;
   for (size_t q = 0; q < live.size(); ++q) {
-    const dl_problem* P = B->probs[live[q]];
-    cost[q] = (double)P->nnz + 64.0 * (double)P->n_tasks;
+    const int i = live[q];
+    if (B->prof[i].ticks.empty()) {
+      cost[q] = B->model_tot[i] * ratio;
+    } else {
+      cost[q] = 0.0;
+      for (double v : B->prof[i].ticks) cost[q] += std::max(v, 1.0);
+    }
     tot += cost[q];
   }
   const int budget = std::max<int>((int)live.size(), B->n_cu * B->wg_per_cu);
@@ -157,6 +227,8 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     B->part_cap = part_need;
   }
   B->h_args.assign(B->n, dl_grad_args());
+  B->live = live;
+  B->wg_first.assign(live.size(), 0);
   for (size_t q = 0; q < live.size(); ++q) {
     const int i = live[q];
     const dl_problem* P = B->probs[i];
@@ -167,15 +239,18 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     dl_grad_args A = dl_make_grad_args(P, mu_y, gamma);
     A.part = B->d_part + part_off[q];
     B->h_args[i] = A;
-    // contiguous task ranges of this instance, balanced by slot count
-    const int64_t T = P->n_tasks;
-    for (int k = 0; k < w[q]; ++k) {
-      dl_wg_desc d;
-      d.inst = i;
-      d.slot = k;
-      d.t0 = T * k / w[q];
-      d.t1 = T * (k + 1) / w[q];
-      B->h_wgs.push_back(d);
+    // contiguous task ranges of this instance with equal estimated time
+    B->wg_first[q] = B->h_wgs.size();
+    if (w[q] > 0) {
+      const std::vector<int64_t> bd = split_tasks(P, w[q], B->prof[i]);
+      for (int k = 0; k < w[q]; ++k) {
+        dl_wg_desc d;
+        d.inst = i;
+        d.slot = k;
+        d.t0 = bd[(size_t)k];
+        d.t1 = bd[(size_t)k + 1];
+        B->h_wgs.push_back(d);
+      }
     }
     bupd u;
     memset(&u, 0, sizeof(u));
@@ -222,6 +297,155 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
   return DL_OK;
 }
 
+// Turns the per-workgroup clock stamps of the batched pass on or off (the
+// stamps of live position q start at workgroup wg_first[q] of the buffer).
+static dl_status set_clocking(dl_batch* B, bool on) {
+  for (size_t q = 0; q < B->live.size(); ++q)
+    B->h_args[B->live[q]].wg_clock = on ? B->d_clock + 2 * B->wg_first[q] : nullptr;
+  DL_HIP_TRY(hipMemcpyAsync(B->d_args, B->h_args.data(), sizeof(dl_grad_args) * B->n, hipMemcpyHostToDevice,
+                            B->stream));
+  DL_HIP_TRY(hipStreamSynchronize(B->stream));
+  return DL_OK;
+}
+
+// Times `reps` batched gradient passes (scale pass included) at the current
+// gather points and reads back every workgroup's duration of the last one.
+// The passes only rewrite the partial slots that the next iteration's pass
+// rewrites anyway, so the solver states are unchanged.
+static dl_status measure_batch(dl_batch* B, int reps, double* ms, std::vector<double>* dur) {
+  const size_t need = 2 * (size_t)std::max(B->n_wg, 1);
+  if (need > B->clock_cap) {
+    DL_HIP_TRY(hipStreamSynchronize(B->stream));
+    if (B->d_clock) DL_HIP_TRY(hipFree(B->d_clock));
+    B->d_clock = nullptr;
+    B->clock_cap = 0;
+    DL_HIP_TRY(hipMalloc((void**)&B->d_clock, need * sizeof(unsigned long long)));
+    B->clock_cap = need;
+  }
+  DL_TRY(set_clocking(B, true));
+  hipEvent_t e0, e1;
+  DL_HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    dl_set_error("hipEventCreate failed");
+    return DL_EHIP;
+  }
+  dl_status rc = DL_OK;
+  if (hipEventRecord(e0, B->stream) != hipSuccess) rc = DL_EHIP;
+  for (int r = 0; r < reps && rc == DL_OK; ++r) {
+    rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
+    if (rc == DL_OK) rc = dl_launch_grad_batch(B->probs[B->live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream);
+  }
+  if (rc == DL_OK && hipEventRecord(e1, B->stream) != hipSuccess) rc = DL_EHIP;
+  std::vector<unsigned long long> clk(need);
+  if (rc == DL_OK && hipMemcpyAsync(clk.data(), B->d_clock, sizeof(unsigned long long) * 2 * B->n_wg,
+                                    hipMemcpyDeviceToHost, B->stream) != hipSuccess)
+    rc = DL_EHIP;
+  if (rc == DL_OK && hipStreamSynchronize(B->stream) != hipSuccess) rc = DL_EHIP;
+  float t = 0.f;
+  if (rc == DL_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = DL_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != DL_OK) {
+    dl_set_error("timing a batched gradient pass failed");
+    return rc;
+  }
+  DL_TRY(set_clocking(B, false));
+  *ms = t / reps;
+  dur->assign((size_t)B->n_wg, 0.0);
+  for (int w = 0; w < B->n_wg; ++w) (*dur)[(size_t)w] = (double)(clk[2 * (size_t)w + 1] - clk[2 * (size_t)w]);
+  return DL_OK;
+}
+
+// The measured profile of the current tables: each live instance's workgroup
+// ranges and their durations.
+static std::vector<inst_profile> profile_of(const dl_batch* B, const std::vector<double>& dur) {
+  std::vector<inst_profile> pr = B->prof;
+  for (size_t q = 0; q < B->live.size(); ++q) {
+    const int i = B->live[q];
+    const size_t f = B->wg_first[q];
+    const size_t e = (q + 1 < B->live.size()) ? B->wg_first[q + 1] : B->h_wgs.size();
+    inst_profile p;
+    if (e > f) {
+      for (size_t w = f; w < e; ++w) {
+        p.b.push_back(B->h_wgs[w].t0);
+        p.ticks.push_back(dur[w]);
+      }
+      p.b.push_back(B->h_wgs[e - 1].t1);
+    }
+    pr[(size_t)i] = p;
+  }
+  return pr;
+}
+
+static double wg_imbalance(const std::vector<double>& d) {
+  if (d.empty()) return 1.0;
+  double mx = 0.0, sum = 0.0;
+  for (double v : d) {
+    mx = std::max(mx, v);
+    sum += v;
+  }
+  return sum > 0 ? mx / (sum / (double)d.size()) : 1.0;
+}
+
+// Re-deals the workgroups of the live instances from measured time: `rounds`
+// times, the batched pass is timed and the split rebuilt from the measured
+// profile; the best split found is timed again against the starting one with
+// more passes, and the faster is kept for the rest of the solve.
+static dl_status tune_batch(dl_batch* B, double gamma, int rounds) {
+  const int reps = 3, final_reps = 10;
+  const std::vector<int> live = B->live;
+  const std::vector<inst_profile> start = B->prof;
+  double ms;
+  std::vector<double> dur;
+  DL_TRY(measure_batch(B, reps, &ms, &dur));
+  dl_tune_result& out = B->tune;
+  memset(&out, 0, sizeof(out));
+  out.rounds = rounds;
+  out.imbalance_model = wg_imbalance(dur);
+  std::vector<inst_profile> best = start;
+  double best_ms = ms, best_imb = out.imbalance_model;
+  bool improved = false;
+  for (int r = 0; r < rounds; ++r) {
+    const std::vector<inst_profile> used = profile_of(B, dur);
+    B->prof = used;
+    DL_TRY(build_tables(B, live, gamma));
+    DL_TRY(measure_batch(B, reps, &ms, &dur));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_imb = wg_imbalance(dur);
+      best = used;
+      improved = true;
+    }
+  }
+  // the starting split and the best one, timed again with more passes (when
+  // no round beat the start, the start is kept without a second timing)
+  B->prof = start;
+  DL_TRY(build_tables(B, live, gamma));
+  DL_TRY(measure_batch(B, final_reps, &ms, &dur));
+  out.pass_ms_model = ms;
+  double kept_ms = ms;
+  if (improved) {
+    B->prof = best;
+    DL_TRY(build_tables(B, live, gamma));
+    double ms_b;
+    DL_TRY(measure_batch(B, final_reps, &ms_b, &dur));
+    if (ms_b < ms) {
+      kept_ms = ms_b;
+      out.imbalance_tuned = best_imb;
+    } else {
+      B->prof = start;
+      DL_TRY(build_tables(B, live, gamma));
+      out.imbalance_tuned = out.imbalance_model;
+    }
+  } else {
+    out.imbalance_tuned = out.imbalance_model;
+  }
+  out.pass_ms_tuned = kept_ms;
+  out.n_workgroups = B->n_wg;
+  return DL_OK;
+}
+
 extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_batch** out) {
   DL_CHECK_ARG(out, "out is NULL");
   *out = nullptr;
@@ -244,6 +468,11 @@ extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_bat
   B->n = n;
   B->probs.assign(probs, probs + n);
   B->stream = P0->stream;
+  B->prof.assign((size_t)n, inst_profile());
+  B->model_tot.assign((size_t)n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (float c : probs[i]->task_cost) B->model_tot[(size_t)i] += c;
+  memset(&B->tune, 0, sizeof(B->tune));
   auto fail = [&](dl_status s) {
     free_batch(B);
     return s;
@@ -262,6 +491,12 @@ extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_bat
 
 extern "C" void dl_batch_destroy(dl_batch* B) { free_batch(B); }
 
+extern "C" dl_status dl_batch_get_tune(const dl_batch* B, dl_tune_result* out) {
+  DL_CHECK_ARG(B && out, "NULL argument");
+  *out = B->tune;
+  return DL_OK;
+}
+
 extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const double* const* lambda0,
                                     double* const* lambda_out, dl_solve_stats* stats) {
   DL_CHECK_ARG(B && o && lambda_out && stats, "NULL argument");
@@ -271,8 +506,12 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
     DL_CHECK_ARG(o->iters[s] >= 0 || s == o->n_stages - 1, "only the last stage may run until tol");
   }
   for (int i = 0; i < B->n; ++i) DL_CHECK_ARG(lambda_out[i], "NULL lambda_out entry");
+  DL_CHECK_ARG(o->max_iters >= 0 && o->check_every >= 0 && o->autotune_rounds >= 0, "negative limits");
   const double step_scale = o->step_scale > 0.0 ? o->step_scale : 1.0;
   auto t0 = std::chrono::steady_clock::now();
+  // every solve starts from the cost-model split
+  B->prof.assign((size_t)B->n, inst_profile());
+  memset(&B->tune, 0, sizeof(B->tune));
   for (dl_solver* s : B->solvers) dl_solver_destroy(s);
   B->solvers.assign(B->n, nullptr);
   for (int i = 0; i < B->n; ++i) {
@@ -299,6 +538,8 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
     const int64_t n_it = o->iters[stage];
     double tk = 1.0;
     int64_t k = 0;
+    // the tuner runs once, after up to 50 iterations of the first stage
+    const int64_t tune_at = (stage == 0 && o->autotune_rounds > 0) ? (n_it < 0 ? 50 : std::min<int64_t>(n_it, 50)) : -1;
     while ((n_it < 0 || k < n_it) && total < o->max_iters && !live.empty()) {
       rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
       if (rc != DL_OK) break;
@@ -317,6 +558,10 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
       ++k;
       ++total;
       for (int i : live) ++iters[i];
+      if (k == tune_at) {
+        rc = tune_batch(B, gamma, o->autotune_rounds);
+        if (rc != DL_OK) break;
+      }
       if (last && o->check_every > 0 && k % o->check_every == 0) {
         std::vector<int> keep;
         for (int i : live) {

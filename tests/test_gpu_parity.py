@@ -466,3 +466,29 @@ def test_batch_matches_solo_solves(dl, orc, wl):
     lo, so, _, _ = orc.solve(members[0], sched["gammas"], sched["iters"], tol=1e-4, max_iters=3000,
                              check_every=10, jacobi=True)
     assert abs(st_b[0]["dual_obj"] - so["dual_obj"]) <= 2e-4 * abs(so["dual_obj"])
+
+
+def test_tuned_batch_matches_solo(dl, wl):
+    """The batch tuner re-deals workgroups between and inside members from measured
+    time after 50 iterations; every member still ends bitwise where its solo solve
+    ends, and the report describes the kept split.  A second solve on the same batch
+    without tuning starts again from the cost model."""
+    members = [wl.batch_member(k, binding=True, scale=0.02) for k in range(6, 12)]
+    sched = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[100, 100, -1], tol=1e-4, max_iters=3000, check_every=10)
+    probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]
+    batch = dl.Batch(probs)
+    lam_b, st_b = batch.solve(autotune=2, **sched)
+    tr = batch.tune()
+    print(f"batch tune: {tr}")
+    assert tr["rounds"] == 2 and tr["n_workgroups"] >= len(members)
+    assert tr["pass_ms_model"] > 0 and 0 < tr["pass_ms_tuned"] <= tr["pass_ms_model"]
+    assert tr["imbalance_tuned"] >= 1.0 and tr["imbalance_model"] >= 1.0
+    for k, (m, p) in enumerate(zip(members, probs)):
+        lam_s, st_s = p.solve(**sched)
+        print(f"member {k}: I={m.n_users} nnz={m.nnz} iters batch {st_b[k]['iters']} solo {st_s['iters']}")
+        assert st_b[k]["iters"] == st_s["iters"]
+        assert np.array_equal(lam_b[k].cpu().numpy(), lam_s.cpu().numpy())
+    lam_u, st_u = batch.solve(**sched)
+    assert batch.tune()["rounds"] == 0
+    for k in range(len(members)):
+        assert np.array_equal(lam_u[k].cpu().numpy(), lam_b[k].cpu().numpy())
