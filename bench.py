@@ -230,6 +230,41 @@ def learned_eval(args, log=log):
             "days": days}
 
 
+def member_rates(members, probs):
+    """Solo gradient-pass time of every batch member (HIP events around 30 passes at
+    gamma 0.1 after 30 untimed iterations) against one batched pass.  Prints its own
+    JSON line."""
+    import torch
+
+    import paper_2606_07777_amd as dl
+    rows = []
+    for m, p in zip(members, probs):
+        s = p.solver()
+        s.set_stage(1e-1)
+        s.step(30)
+        s.enable_timing(True)
+        s.step(30)
+        t = s.timing()
+        ms = t["grad_ms_total"] / t["n_grad"]
+        rows.append({"users": m.n_users, "items": m.n_items, "nnz": m.nnz, "pass_ms": ms,
+                     "GBps": (8.0 * m.nnz + 8.0 * (m.n_users + 1)) / (ms * 1e-3) / 1e9})
+        del s
+    batch = dl.Batch(probs)
+    _, _ = batch.solve(gammas=[1e-1], iters=[60], check_every=0, autotune=1)
+    torch.cuda.synchronize()
+    tr = batch.tune()
+    nnz = sum(r["nnz"] for r in rows)
+    solo_ms = sum(r["pass_ms"] for r in rows)
+    for r in rows:
+        log(f"member I={r['users']} J={r['items']} nnz={r['nnz']}: {r['pass_ms']:.4f} ms, {r['GBps']:.0f} GB/s")
+    out = {"metric": "gradient-pass time of the uneven batch members, solo vs one batched pass", "unit": "ms",
+           "solo_sum_ms": solo_ms, "batched_pass_ms": tr["pass_ms_model"],
+           "solo_GBps_min": min(r["GBps"] for r in rows), "solo_GBps_max": max(r["GBps"] for r in rows),
+           "batched_GBps": 8.0 * nnz / (tr["pass_ms_model"] * 1e-3) / 1e9, "members": rows,
+           "config": {"workload": f"uneven batch of {len(members)}"}}
+    print(json.dumps(out), flush=True)
+
+
 def batch_bench(args):
     """The uneven batch: 64 instances (users log-uniform in [5e4, 2e6], items
     log-uniform in [100, 5000], degree round(lognormal(3.5, 0.8)), uniform items,
@@ -250,6 +285,8 @@ def batch_bench(args):
         f"in {time.time() - t:.1f}s")
     torch.cuda.set_device(0)
     probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]
+    if args.member_rates:
+        return member_rates(members, probs)
     sched = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[300, 300, -1], tol=1e-4, max_iters=20000, check_every=10)
     batch = dl.Batch(probs)
     torch.cuda.synchronize()
@@ -305,6 +342,8 @@ def main():
                     help="also run the six-stage gamma schedule 1e3..1e-2 with this many iterations per stage")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--member-rates", action="store_true",
+                    help="with --workload batch: per-member solo pass rates against one batched pass")
     ap.add_argument("--batch-tune", type=int, default=2,
                     help="balancing rounds of the batch tuner (0: cost-model split only)")
     ap.add_argument("--users", type=int, default=10_000_000)
