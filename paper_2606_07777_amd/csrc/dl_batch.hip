@@ -514,9 +514,14 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
   memset(&B->tune, 0, sizeof(B->tune));
   for (dl_solver* s : B->solvers) dl_solver_destroy(s);
   B->solvers.assign(B->n, nullptr);
+  for (int i = 0; i < B->n; ++i) memset(&stats[i], 0, sizeof(stats[i]));
   for (int i = 0; i < B->n; ++i) {
-    memset(&stats[i], 0, sizeof(stats[i]));
-    DL_TRY(dl_solver_create(B->probs[i], lambda0 ? lambda0[i] : nullptr, &B->solvers[i]));
+    const dl_status cs = dl_solver_create(B->probs[i], lambda0 ? lambda0[i] : nullptr, &B->solvers[i]);
+    if (cs != DL_OK) {
+      for (dl_solver* s : B->solvers) dl_solver_destroy(s);
+      B->solvers.clear();
+      return cs;
+    }
   }
   std::vector<int> live(B->n);
   std::iota(live.begin(), live.end(), 0);
@@ -533,7 +538,8 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
       last_stage[i] = stage;
     }
     if (rc != DL_OK) break;
-    DL_TRY(build_tables(B, live, gamma));
+    rc = build_tables(B, live, gamma);
+    if (rc != DL_OK) break;
     const bool last = stage == o->n_stages - 1;
     const int64_t n_it = o->iters[stage];
     double tk = 1.0;
@@ -581,7 +587,10 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
         }
         if (keep.size() != live.size()) {
           live = keep;
-          if (!live.empty()) DL_TRY(build_tables(B, live, gamma));
+          if (!live.empty()) {
+            rc = build_tables(B, live, gamma);
+            if (rc != DL_OK) break;
+          }
         }
       }
       if (n_it < 0 && o->check_every == 0 && total >= o->max_iters) break;
@@ -596,7 +605,10 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
     dl_status ls = dl_solver_get_lambda(B->solvers[i], lambda_out[i]);
     if (ls != DL_OK) rc = ls;
   }
-  if (rc == DL_OK) DL_HIP_TRY(hipStreamSynchronize(B->stream));
+  if (rc == DL_OK && hipStreamSynchronize(B->stream) != hipSuccess) {
+    dl_set_error("hipStreamSynchronize failed");
+    rc = DL_EHIP;
+  }
   const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   bool all_ok = true;
   for (int i = 0; i < B->n; ++i) {
