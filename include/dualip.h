@@ -262,12 +262,13 @@ void dl_batch_destroy(dl_batch* batch); /* NULL-safe; does not destroy the probl
  * dealt by pass cost) plus one update launch.  Members leave the launch when
  * their certified gap reaches tol at a check point of the final stage.
  * With opts->autotune_rounds > 0 the pass cost is measured once, after up to
- * 50 iterations of the first stage: the batched pass is timed with per-
- * workgroup clock stamps and the workgroups are re-dealt (between members and
- * inside each) from the measured times that many times; the faster of the
- * best re-dealt split and the cost-model split is kept for the rest of the
- * solve (dl_batch_get_tune reports it).  The split never changes a member's
- * iterates: they stay bitwise equal to its solo solve.
+ * 50 iterations of the first stage: for grids of 1, 2 and 4 workgroups per
+ * compute unit, the batched pass is timed with per-workgroup clock stamps and
+ * the workgroups are re-dealt (between members and inside each) from the
+ * measured times that many times; the faster of the best configuration found
+ * and the starting one (cost model, 4 per compute unit) is kept for the rest
+ * of the solve (dl_batch_get_tune reports it).  The split never changes a
+ * member's iterates: they stay bitwise equal to its solo solve.
  *   lambda0     host array of n device pointers (m_i*J_i each), or NULL (zeros)
  *   lambda_out  host array of n device pointers (m_i*J_i each)
  *   stats       host array of n records (iters and status per member)

@@ -388,44 +388,64 @@ static double wg_imbalance(const std::vector<double>& d) {
   return sum > 0 ? mx / (sum / (double)d.size()) : 1.0;
 }
 
-// Re-deals the workgroups of the live instances from measured time: `rounds`
-// times, the batched pass is timed and the split rebuilt from the measured
-// profile; the best split found is timed again against the starting one with
-// more passes, and the faster is kept for the rest of the solve.
+// Re-deals the workgroups of the live instances from measured time.  For
+// grids of 1, 2 and 4 workgroups per compute unit, the batched pass is timed
+// from the cost-model split and the split is rebuilt from the measured profile
+// `rounds` times.  The fastest configuration found is timed again against the
+// starting one (cost model, 4 per compute unit) with more passes, and the
+// faster of the two is kept for the rest of the solve.
 static dl_status tune_batch(dl_batch* B, double gamma, int rounds) {
   const int reps = 3, final_reps = 10;
   const std::vector<int> live = B->live;
   const std::vector<inst_profile> start = B->prof;
-  double ms;
-  std::vector<double> dur;
-  DL_TRY(measure_batch(B, reps, &ms, &dur));
+  const int start_wpc = B->wg_per_cu;
   dl_tune_result& out = B->tune;
   memset(&out, 0, sizeof(out));
   out.rounds = rounds;
-  out.imbalance_model = wg_imbalance(dur);
+  double ms;
+  std::vector<double> dur;
   std::vector<inst_profile> best = start;
-  double best_ms = ms, best_imb = out.imbalance_model;
+  int best_wpc = start_wpc;
+  double best_ms = 1e300, best_imb = 1.0;
   bool improved = false;
-  for (int r = 0; r < rounds; ++r) {
-    const std::vector<inst_profile> used = profile_of(B, dur);
-    B->prof = used;
+  for (int wpc = 1; wpc <= 4; wpc *= 2) {
+    B->wg_per_cu = wpc;
+    B->prof = start;
     DL_TRY(build_tables(B, live, gamma));
     DL_TRY(measure_batch(B, reps, &ms, &dur));
+    if (wpc == start_wpc) out.imbalance_model = wg_imbalance(dur);
     if (ms < best_ms) {
       best_ms = ms;
       best_imb = wg_imbalance(dur);
-      best = used;
-      improved = true;
+      best = start;
+      best_wpc = wpc;
+      improved = wpc != start_wpc;
+    }
+    for (int r = 0; r < rounds; ++r) {
+      const std::vector<inst_profile> used = profile_of(B, dur);
+      B->prof = used;
+      DL_TRY(build_tables(B, live, gamma));
+      DL_TRY(measure_batch(B, reps, &ms, &dur));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_imb = wg_imbalance(dur);
+        best = used;
+        best_wpc = wpc;
+        improved = true;
+      }
     }
   }
-  // the starting split and the best one, timed again with more passes (when
-  // no round beat the start, the start is kept without a second timing)
+  // the starting configuration and the best one, timed again with more passes
+  // (when nothing beat the start, it is kept without a second timing)
+  B->wg_per_cu = start_wpc;
   B->prof = start;
   DL_TRY(build_tables(B, live, gamma));
   DL_TRY(measure_batch(B, final_reps, &ms, &dur));
   out.pass_ms_model = ms;
   double kept_ms = ms;
+  out.imbalance_tuned = out.imbalance_model;
   if (improved) {
+    B->wg_per_cu = best_wpc;
     B->prof = best;
     DL_TRY(build_tables(B, live, gamma));
     double ms_b;
@@ -434,12 +454,10 @@ static dl_status tune_batch(dl_batch* B, double gamma, int rounds) {
       kept_ms = ms_b;
       out.imbalance_tuned = best_imb;
     } else {
+      B->wg_per_cu = start_wpc;
       B->prof = start;
       DL_TRY(build_tables(B, live, gamma));
-      out.imbalance_tuned = out.imbalance_model;
     }
-  } else {
-    out.imbalance_tuned = out.imbalance_model;
   }
   out.pass_ms_tuned = kept_ms;
   out.n_workgroups = B->n_wg;
@@ -509,8 +527,9 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
   DL_CHECK_ARG(o->max_iters >= 0 && o->check_every >= 0 && o->autotune_rounds >= 0, "negative limits");
   const double step_scale = o->step_scale > 0.0 ? o->step_scale : 1.0;
   auto t0 = std::chrono::steady_clock::now();
-  // every solve starts from the cost-model split
+  // every solve starts from the cost-model split, 4 workgroups per compute unit
   B->prof.assign((size_t)B->n, inst_profile());
+  B->wg_per_cu = 4;
   memset(&B->tune, 0, sizeof(B->tune));
   for (dl_solver* s : B->solvers) dl_solver_destroy(s);
   B->solvers.assign(B->n, nullptr);
