@@ -109,6 +109,7 @@ struct dl_batch {
   // per-workgroup (start, end) clock stamps of a timed pass, 2 * clock_cap
   unsigned long long* d_clock = nullptr;
   size_t clock_cap = 0;
+  std::vector<std::vector<double>> cmodel;  // per instance: prefix sums of its tasks' model weights
   std::vector<double> model_tot;   // per instance: total cost-model weight of its tasks
   std::vector<inst_profile> prof;  // per instance: measured cost profile (empty: cost model)
   dl_tune_result tune;             // last tuning result (zeros before any)
@@ -125,37 +126,45 @@ static void free_batch(dl_batch* B) {
 
 // Task boundaries of w workgroups over one instance with equal estimated time.
 // A task weighs its cost-model weight; inside each measured range the weights
-// are scaled so that the range adds up to its measured time.
-static std::vector<int64_t> split_tasks(const dl_problem* P, int w, const inst_profile& pr) {
+// are scaled so that the range adds up to its measured time.  `cm` holds the
+// prefix sums of the model weights (T + 1 entries).  A boundary falls before
+// the first task whose weight midpoint reaches the target, found by binary
+// search on the (nondecreasing) weighted prefix sum.
+static std::vector<int64_t> split_tasks(const dl_problem* P, int w, const inst_profile& pr,
+                                        const std::vector<double>& cm) {
   const int64_t T = P->n_tasks;
-  std::vector<double> f;  // per measured range: ticks per unit of model weight
-  if (!pr.ticks.empty()) {
-    f.resize(pr.ticks.size());
-    for (size_t k = 0; k < pr.ticks.size(); ++k) {
-      double mc = 0.0;
-      for (int64_t t = pr.b[k]; t < pr.b[k + 1]; ++t) mc += P->task_cost[(size_t)t];
-      f[k] = mc > 0.0 ? std::max(pr.ticks[k], 1.0) / mc : 0.0;
-    }
+  const size_t K = pr.ticks.size();
+  // per measured range: ticks per unit of model weight, and the weighted sum before it
+  std::vector<double> f(K), before(K + 1, 0.0);
+  for (size_t k = 0; k < K; ++k) {
+    const double mc = cm[(size_t)pr.b[k + 1]] - cm[(size_t)pr.b[k]];
+    f[k] = mc > 0.0 ? std::max(pr.ticks[k], 1.0) / mc : 0.0;
+    before[k + 1] = before[k] + f[k] * mc;
   }
-  std::vector<double> wt((size_t)T);
-  double tot = 0.0;
-  size_t k = 0;
-  for (int64_t t = 0; t < T; ++t) {
-    double c = P->task_cost[(size_t)t];
-    if (!f.empty()) {
-      while (k + 1 < f.size() && t >= pr.b[k + 1]) ++k;
-      c *= f[k];
-    }
-    wt[(size_t)t] = c;
-    tot += c;
-  }
+  // weighted prefix sum over tasks [0, t)
+  auto W = [&](int64_t t) -> double {
+    if (K == 0) return cm[(size_t)t];
+    // the range holding task t: the last k with b[k] <= t (t == T: the end)
+    const size_t k = (size_t)(std::upper_bound(pr.b.begin(), pr.b.end() - 1, t) - pr.b.begin()) - 1;
+    if (k >= K) return before[K];
+    return before[k] + f[k] * (cm[(size_t)t] - cm[(size_t)pr.b[k]]);
+  };
+  const double tot = W(T);
   std::vector<int64_t> bounds((size_t)w + 1, 0);
-  double run = 0.0;
-  int64_t t = 0;
+  int64_t lo = 0;
   for (int q = 1; q < w; ++q) {
     const double target = tot * (double)q / (double)w;
-    while (t < T && run + 0.5 * wt[(size_t)t] < target) run += wt[(size_t)t++];
-    bounds[(size_t)q] = t;
+    // smallest t in [lo, T) with 0.5 (W(t) + W(t + 1)) >= target, else T
+    int64_t a = lo, b = T;
+    while (a < b) {
+      const int64_t mid = a + (b - a) / 2;
+      if (0.5 * (W(mid) + W(mid + 1)) < target)
+        a = mid + 1;
+      else
+        b = mid;
+    }
+    bounds[(size_t)q] = a;
+    lo = a;
   }
   bounds[(size_t)w] = T;
   return bounds;
@@ -242,7 +251,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     // contiguous task ranges of this instance with equal estimated time
     B->wg_first[q] = B->h_wgs.size();
     if (w[q] > 0) {
-      const std::vector<int64_t> bd = split_tasks(P, w[q], B->prof[i]);
+      const std::vector<int64_t> bd = split_tasks(P, w[q], B->prof[i], B->cmodel[i]);
       for (int k = 0; k < w[q]; ++k) {
         dl_wg_desc d;
         d.inst = i;
@@ -488,8 +497,14 @@ extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_bat
   B->stream = P0->stream;
   B->prof.assign((size_t)n, inst_profile());
   B->model_tot.assign((size_t)n, 0.0);
-  for (int i = 0; i < n; ++i)
-    for (float c : probs[i]->task_cost) B->model_tot[(size_t)i] += c;
+  B->cmodel.assign((size_t)n, std::vector<double>());
+  for (int i = 0; i < n; ++i) {
+    const std::vector<float>& tc = probs[i]->task_cost;
+    std::vector<double>& c = B->cmodel[(size_t)i];
+    c.assign(tc.size() + 1, 0.0);
+    for (size_t t = 0; t < tc.size(); ++t) c[t + 1] = c[t] + tc[t];
+    B->model_tot[(size_t)i] = c.back();
+  }
   memset(&B->tune, 0, sizeof(B->tune));
   auto fail = [&](dl_status s) {
     free_batch(B);
