@@ -324,12 +324,22 @@ def batch_bench(args):
     torch.cuda.synchronize()
     t_solo = time.perf_counter() - t0
     log(f"solo: {t_solo:.2f}s")
+    # the solo solves again with each problem's own workgroup tuner (it keeps the
+    # tuned split on the problem, so this runs after the untuned solves)
+    t0 = time.perf_counter()
+    st_st = []
+    for p in probs:
+        st_st.append(p.solve(autotune_rounds=2, **sched)[1])
+    torch.cuda.synchronize()
+    t_solo_tuned = time.perf_counter() - t0
+    log(f"solo, tuned: {t_solo_tuned:.2f}s")
     work_b = sum(n * s["iters"] for n, s in zip(nnz, st_b))
     work_s = sum(n * s["iters"] for n, s in zip(nnz, st_s))
-    same = all(a["iters"] == b["iters"] == c["iters"] for a, b, c in zip(st_b, st_s, st_t))
+    same = all(a["iters"] == b["iters"] == c["iters"] == d["iters"] for a, b, c, d in zip(st_b, st_s, st_t, st_st))
     out = {"metric": "time to a 1e-4 gap for every member of the uneven batch", "unit": "s",
            "batch_s": t_batch, "batch_tuned_s": t_tuned, "batch_tuner": tune,
            "solo_sequential_s": t_solo, "speedup": t_solo / t_batch,
+           "solo_sequential_tuned_s": t_solo_tuned, "speedup_vs_tuned_solo": t_solo_tuned / t_batch,
            "batch_nnz_iter_per_s": work_b / t_batch, "solo_nnz_iter_per_s": work_s / t_solo,
            "same_iterations_as_solo": same, "members": len(members), "nnz": int(sum(nnz)),
            "converged": int(sum(s["status"] == 0 for s in st_b)),
