@@ -20,6 +20,7 @@
 #include <numeric>
 
 #include "dl_common.h"
+#include "dl_split.h"
 
 struct dl_solver;  // dl_solver.hip
 dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag);
@@ -74,13 +75,6 @@ __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict_
   if (!isfinite(ln) || !isfinite(yn)) atomicOr(u.flag, 1);
 }
 
-// Measured cost of one instance's pass: workgroup ranges [b[k], b[k+1]) and
-// the clock ticks each took.  Empty = not measured.
-struct inst_profile {
-  std::vector<int64_t> b;
-  std::vector<double> ticks;
-};
-
 }  // namespace
 
 struct dl_batch {
@@ -111,7 +105,7 @@ struct dl_batch {
   size_t clock_cap = 0;
   std::vector<std::vector<double>> cmodel;  // per instance: prefix sums of its tasks' model weights
   std::vector<double> model_tot;   // per instance: total cost-model weight of its tasks
-  std::vector<inst_profile> prof;  // per instance: measured cost profile (empty: cost model)
+  std::vector<dl_inst_profile> prof;  // per instance: measured cost profile (empty: cost model)
   dl_tune_result tune;             // last tuning result (zeros before any)
 };
 
@@ -122,52 +116,6 @@ static void free_batch(dl_batch* B) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete B;
-}
-
-// Task boundaries of w workgroups over one instance with equal estimated time.
-// A task weighs its cost-model weight; inside each measured range the weights
-// are scaled so that the range adds up to its measured time.  `cm` holds the
-// prefix sums of the model weights (T + 1 entries).  A boundary falls before
-// the first task whose weight midpoint reaches the target, found by binary
-// search on the (nondecreasing) weighted prefix sum.
-static std::vector<int64_t> split_tasks(const dl_problem* P, int w, const inst_profile& pr,
-                                        const std::vector<double>& cm) {
-  const int64_t T = P->n_tasks;
-  const size_t K = pr.ticks.size();
-  // per measured range: ticks per unit of model weight, and the weighted sum before it
-  std::vector<double> f(K), before(K + 1, 0.0);
-  for (size_t k = 0; k < K; ++k) {
-    const double mc = cm[(size_t)pr.b[k + 1]] - cm[(size_t)pr.b[k]];
-    f[k] = mc > 0.0 ? std::max(pr.ticks[k], 1.0) / mc : 0.0;
-    before[k + 1] = before[k] + f[k] * mc;
-  }
-  // weighted prefix sum over tasks [0, t)
-  auto W = [&](int64_t t) -> double {
-    if (K == 0) return cm[(size_t)t];
-    // the range holding task t: the last k with b[k] <= t (t == T: the end)
-    const size_t k = (size_t)(std::upper_bound(pr.b.begin(), pr.b.end() - 1, t) - pr.b.begin()) - 1;
-    if (k >= K) return before[K];
-    return before[k] + f[k] * (cm[(size_t)t] - cm[(size_t)pr.b[k]]);
-  };
-  const double tot = W(T);
-  std::vector<int64_t> bounds((size_t)w + 1, 0);
-  int64_t lo = 0;
-  for (int q = 1; q < w; ++q) {
-    const double target = tot * (double)q / (double)w;
-    // smallest t in [lo, T) with 0.5 (W(t) + W(t + 1)) >= target, else T
-    int64_t a = lo, b = T;
-    while (a < b) {
-      const int64_t mid = a + (b - a) / 2;
-      if (0.5 * (W(mid) + W(mid + 1)) < target)
-        a = mid + 1;
-      else
-        b = mid;
-    }
-    bounds[(size_t)q] = a;
-    lo = a;
-  }
-  bounds[(size_t)w] = T;
-  return bounds;
 }
 
 // Rebuilds the launch tables for the live instances at gamma.
@@ -251,7 +199,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     // contiguous task ranges of this instance with equal estimated time
     B->wg_first[q] = B->h_wgs.size();
     if (w[q] > 0) {
-      const std::vector<int64_t> bd = split_tasks(P, w[q], B->prof[i], B->cmodel[i]);
+      const std::vector<int64_t> bd = dl_split_tasks(w[q], B->prof[i], B->cmodel[i]);
       for (int k = 0; k < w[q]; ++k) {
         dl_wg_desc d;
         d.inst = i;
@@ -368,13 +316,13 @@ static dl_status measure_batch(dl_batch* B, int reps, double* ms, std::vector<do
 
 // The measured profile of the current tables: each live instance's workgroup
 // ranges and their durations.
-static std::vector<inst_profile> profile_of(const dl_batch* B, const std::vector<double>& dur) {
-  std::vector<inst_profile> pr = B->prof;
+static std::vector<dl_inst_profile> profile_of(const dl_batch* B, const std::vector<double>& dur) {
+  std::vector<dl_inst_profile> pr = B->prof;
   for (size_t q = 0; q < B->live.size(); ++q) {
     const int i = B->live[q];
     const size_t f = B->wg_first[q];
     const size_t e = (q + 1 < B->live.size()) ? B->wg_first[q + 1] : B->h_wgs.size();
-    inst_profile p;
+    dl_inst_profile p;
     if (e > f) {
       for (size_t w = f; w < e; ++w) {
         p.b.push_back(B->h_wgs[w].t0);
@@ -406,14 +354,14 @@ static double wg_imbalance(const std::vector<double>& d) {
 static dl_status tune_batch(dl_batch* B, double gamma, int rounds) {
   const int reps = 3, final_reps = 10;
   const std::vector<int> live = B->live;
-  const std::vector<inst_profile> start = B->prof;
+  const std::vector<dl_inst_profile> start = B->prof;
   const int start_wpc = B->wg_per_cu;
   dl_tune_result& out = B->tune;
   memset(&out, 0, sizeof(out));
   out.rounds = rounds;
   double ms;
   std::vector<double> dur;
-  std::vector<inst_profile> best = start;
+  std::vector<dl_inst_profile> best = start;
   int best_wpc = start_wpc;
   double best_ms = 1e300, best_imb = 1.0;
   bool improved = false;
@@ -431,7 +379,7 @@ static dl_status tune_batch(dl_batch* B, double gamma, int rounds) {
       improved = wpc != start_wpc;
     }
     for (int r = 0; r < rounds; ++r) {
-      const std::vector<inst_profile> used = profile_of(B, dur);
+      const std::vector<dl_inst_profile> used = profile_of(B, dur);
       B->prof = used;
       DL_TRY(build_tables(B, live, gamma));
       DL_TRY(measure_batch(B, reps, &ms, &dur));
@@ -495,7 +443,7 @@ extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_bat
   B->n = n;
   B->probs.assign(probs, probs + n);
   B->stream = P0->stream;
-  B->prof.assign((size_t)n, inst_profile());
+  B->prof.assign((size_t)n, dl_inst_profile());
   B->model_tot.assign((size_t)n, 0.0);
   B->cmodel.assign((size_t)n, std::vector<double>());
   for (int i = 0; i < n; ++i) {
@@ -543,7 +491,7 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
   const double step_scale = o->step_scale > 0.0 ? o->step_scale : 1.0;
   auto t0 = std::chrono::steady_clock::now();
   // every solve starts from the cost-model split, 4 workgroups per compute unit
-  B->prof.assign((size_t)B->n, inst_profile());
+  B->prof.assign((size_t)B->n, dl_inst_profile());
   B->wg_per_cu = 4;
   memset(&B->tune, 0, sizeof(B->tune));
   for (dl_solver* s : B->solvers) dl_solver_destroy(s);
