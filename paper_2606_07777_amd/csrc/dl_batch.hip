@@ -100,7 +100,7 @@ struct dl_batch {
   std::vector<bblk> h_blk;
   std::vector<int> live;           // the instances the tables were built for
   std::vector<size_t> wg_first;    // per live position: its first workgroup in h_wgs
-  // per-workgroup (start, end) clock stamps of a timed pass, 2 * clock_cap
+  // per-workgroup (start, end) clock stamps of a timed pass; clock_cap entries
   unsigned long long* d_clock = nullptr;
   size_t clock_cap = 0;
   std::vector<std::vector<double>> cmodel;  // per instance: prefix sums of its tasks' model weights
