@@ -51,7 +51,7 @@ def make_instance(args):
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha1()
-    for f in ("dl_grad.hip", "dl_common.h"):
+    for f in ("dl_grad.hip", "dl_grad_kernels.h", "dl_grad_variant.hip", "dl_common.h"):
         h.update(open(os.path.join(ROOT, "paper_2606_07777_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -11,6 +11,18 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdualip.so")
 SOURCES = ["dl_problem.hip", "dl_grad.hip", "dl_solver.hip", "dl_batch.hip", "dl_mlp.hip"]
+# The gradient-pass kernels are compiled once per variant (families class,
+# stored a, BF16 storage), each build its own object, so they compile in parallel.
+GRAD_VARIANTS = [(1, 0, 0), (1, 0, 1), (1, 1, 0), (1, 1, 1), (4, 1, 0), (4, 1, 1)]
+
+
+def _units():
+    units = [(src, src.replace(".hip", ".o"), []) for src in SOURCES]
+    for mf, a, bf in GRAD_VARIANTS:
+        units.append(("dl_grad_variant.hip", f"dl_grad_v_{mf}_{a}_{bf}.o",
+                      [f"DL_GV_MF={mf}", f"DL_GV_A={a}", f"DL_GV_BF16={bf}"]))
+    return units
+
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -31,14 +43,14 @@ def build(verbose: bool = False, out: str = LIB, defines=(), objdir: str = None)
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+    for src, oname, unit_defs in _units():
+        obj = os.path.join(objdir, oname)
         objs.append(obj)
-        cmd = [hipcc, *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-I", INCLUDE, "-I", CSRC, "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPCC_FLAGS, *[f"-D{d}" for d in (*defines, *unit_defs)], "-I", INCLUDE, "-I", CSRC,
+               "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        procs.append((oname, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
     failed = []
     for src, p in procs:
         log, _ = p.communicate()

@@ -28,778 +28,25 @@
 //    workgroup and summed over workgroups by the update kernel.
 #include <string.h>
 
+#include <type_traits>
+
 #include "dl_common.h"
 
+// The kernel variants (dl_grad_variant.hip, one object per variant).
+#define DL_GV_DECL(mf, a, bf)                                                                              \
+  dl_status dl_grad_launch_v_##mf##_##a##_##bf(const dl_problem*, int, const dl_grad_args&, size_t);       \
+  dl_status dl_grad_batch_v_##mf##_##a##_##bf(const dl_problem*, int, const dl_grad_args*, const dl_wg_desc*, \
+                                              size_t, hipStream_t);                                         \
+  void dl_grad_attr_v_##mf##_##a##_##bf();
+DL_GV_DECL(1, 0, 0)
+DL_GV_DECL(1, 0, 1)
+DL_GV_DECL(1, 1, 0)
+DL_GV_DECL(1, 1, 1)
+DL_GV_DECL(4, 1, 0)
+DL_GV_DECL(4, 1, 1)
+#undef DL_GV_DECL
+
 namespace {
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ float swz_xor16(float v) {
-  // ds_swizzle bit mode: and_mask 0x1F, or_mask 0, xor_mask 0x10 (within 32 lanes)
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
-}
-
-// One butterfly step of an all-reduce over aligned groups of 2^(STEP+1) lanes.
-template <int STEP>
-__device__ __forceinline__ float xstep(float v) {
-  if constexpr (STEP == 0) return dpp_f<0xB1>(v);   // quad_perm(1,0,3,2): lane ^ 1
-  if constexpr (STEP == 1) return dpp_f<0x4E>(v);   // quad_perm(2,3,0,1): lane ^ 2
-  if constexpr (STEP == 2) return dpp_f<0x141>(v);  // row_half_mirror: pairs the two quads of 8
-  if constexpr (STEP == 3) return dpp_f<0x140>(v);  // row_mirror: pairs the two halves of 16
-  if constexpr (STEP == 4) return swz_xor16(v);
-  return __shfl_xor(v, 32, 64);
-}
-
-// All-reduce (sum / max / min) over aligned groups of 2^GLOG lanes.  Every lane
-// of a group ends with the same bits (each step combines the same two operands).
-template <int GLOG>
-__device__ __forceinline__ float gsum(float v) {
-  if constexpr (GLOG > 0) v += xstep<0>(v);
-  if constexpr (GLOG > 1) v += xstep<1>(v);
-  if constexpr (GLOG > 2) v += xstep<2>(v);
-  if constexpr (GLOG > 3) v += xstep<3>(v);
-  if constexpr (GLOG > 4) v += xstep<4>(v);
-  if constexpr (GLOG > 5) v += xstep<5>(v);
-  return v;
-}
-template <int GLOG>
-__device__ __forceinline__ float gmax(float v) {
-  if constexpr (GLOG > 0) v = fmaxf(v, xstep<0>(v));
-  if constexpr (GLOG > 1) v = fmaxf(v, xstep<1>(v));
-  if constexpr (GLOG > 2) v = fmaxf(v, xstep<2>(v));
-  if constexpr (GLOG > 3) v = fmaxf(v, xstep<3>(v));
-  if constexpr (GLOG > 4) v = fmaxf(v, xstep<4>(v));
-  if constexpr (GLOG > 5) v = fmaxf(v, xstep<5>(v));
-  return v;
-}
-template <int GLOG>
-__device__ __forceinline__ float gmin(float v) {
-  if constexpr (GLOG > 0) v = fminf(v, xstep<0>(v));
-  if constexpr (GLOG > 1) v = fminf(v, xstep<1>(v));
-  if constexpr (GLOG > 2) v = fminf(v, xstep<2>(v));
-  if constexpr (GLOG > 3) v = fminf(v, xstep<3>(v));
-  if constexpr (GLOG > 4) v = fminf(v, xstep<4>(v));
-  if constexpr (GLOG > 5) v = fminf(v, xstep<5>(v));
-  return v;
-}
-// (largest, second largest) over the group
-template <int STEP>
-__device__ __forceinline__ void top2_step(float& m1, float& m2) {
-  const float o1 = xstep<STEP>(m1), o2 = xstep<STEP>(m2);
-  const float hi = fmaxf(m1, o1), lo = fminf(m1, o1);
-  m2 = fmaxf(lo, fmaxf(m2, o2));
-  m1 = hi;
-}
-template <int GLOG>
-__device__ __forceinline__ void gtop2(float& m1, float& m2) {
-  if constexpr (GLOG > 0) top2_step<0>(m1, m2);
-  if constexpr (GLOG > 1) top2_step<1>(m1, m2);
-  if constexpr (GLOG > 2) top2_step<2>(m1, m2);
-  if constexpr (GLOG > 3) top2_step<3>(m1, m2);
-  if constexpr (GLOG > 4) top2_step<4>(m1, m2);
-  if constexpr (GLOG > 5) top2_step<5>(m1, m2);
-}
-
-template <typename TV>
-__device__ __forceinline__ float ldv(const TV* p);
-template <>
-__device__ __forceinline__ float ldv<float>(const float* p) {
-  return *p;
-}
-template <>
-__device__ __forceinline__ float ldv<uint16_t>(const uint16_t* p) {
-  return __uint_as_float((uint32_t)(*p) << 16);
-}
-
-__device__ __forceinline__ void hist_add(unsigned long long* h, int r, float w, float qs) {
-  int q = __float2int_rn(w * qs);
-  if (q != 0) atomicAdd(h + r, (unsigned long long)(long long)q);
-}
-
-// w >= 0 (families with a == 1): rounds half up with one fused multiply-add and
-// a truncating convert; the 64-bit addend has a zero high word.
-__device__ __forceinline__ void hist_add_pos(unsigned long long* h, int r, float w, float qs) {
-  const uint32_t q = __float2uint_rz(fmaf(w, qs, 0.5f));
-  if (q != 0) atomicAdd(h + r, (unsigned long long)q);
-}
-
-// ---------------------------------------------------------------------------
-// Group path: 2^GLOG lanes per user, up to KMAX elements per lane.
-// ---------------------------------------------------------------------------
-// Per-lane element loops run in chunks of 4: a chunk runs when its first
-// element is below the task's K (uniform), elements past the row end inside a
-// chunk are masked.  Whole chunks let the compiler batch loads and LDS reads.
-#define DL_FOR_K(k, KMAX, K)                                   \
-  _Pragma("unroll") for (int kc_ = 0; kc_ < (KMAX); kc_ += 4)  \
-    if (kc_ < (K))                                             \
-      _Pragma("unroll") for (int k = kc_; k < kc_ + 4; ++k)
-// Arithmetic loops: chunks of DL_CHUNK, or of 2 with stored a (whose larger
-// register set would otherwise spill in the batched kernel).
-template <bool HAS_A>
-constexpr int chunk_of() { return HAS_A ? 2 : DL_CHUNK; }
-#define DL_FOR_KC(k, KMAX, K)                                                             \
-  _Pragma("unroll") for (int kc_ = 0; kc_ < (KMAX); kc_ += chunk_of<HAS_A>())             \
-    if (kc_ < (K))                                                                        \
-      _Pragma("unroll") for (int k = kc_; k < kc_ + chunk_of<HAS_A>(); ++k)
-
-struct TaskMeta {
-  int64_t s;   // row start (0 for lanes without a user)
-  int64_t e;   // row end (0 for lanes without a user); the length is taken late so
-               // the row-pointer load is not waited on where it is issued
-  int64_t os;  // row start in the caller's order
-};
-
-template <int GLOG>
-__device__ __forceinline__ TaskMeta load_meta(const dl_grad_args& A, const dl_bucket& B, int64_t t, int lane,
-                                              bool need_os) {
-  const int64_t u = B.user_begin + (t - B.task_begin) * (int64_t)(64 >> GLOG) + (lane >> GLOG);
-  TaskMeta m;
-  m.s = 0;
-  m.e = 0;
-  m.os = 0;
-  if (u < B.user_end) {
-    m.s = A.rp[u];
-    m.e = A.rp[u + 1];
-    if (need_os) m.os = A.orig_rp[u];
-  }
-  return m;
-}
-
-template <int MF, bool HAS_A, int KMAX>
-struct RowRegs {
-  int j[KMAX];
-  float c[KMAX];  // c, replaced in place by v
-  float a[HAS_A ? MF : 1][KMAX];
-};
-
-// Issues the loads of one task's rows (lane element e = lid + k*G, k < K).
-// Reads past a row end stay inside the padded arrays and are masked later.
-template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
-                                          RowRegs<MF, HAS_A, KMAX>& R) {
-  constexpr int G = 1 << GLOG;
-  K = __builtin_amdgcn_readfirstlane(K);
-  if constexpr ((MODE & M_VIN) != 0) {
-    const int d = (int)(m.e - m.s);
-    const float* vp = A.v_in + m.os + lid;
-    DL_FOR_K(k, KMAX, K) R.c[k] = (lid + k * G < d) ? vp[k * G] : 0.f;
-    return;
-  }
-  const int32_t* ip = A.idx + m.s + lid;
-  const TV* cp = reinterpret_cast<const TV*>(A.cval) + m.s + lid;
-  DL_FOR_K(k, KMAX, K) {
-    R.j[k] = ip[k * G];
-    R.c[k] = ldv<TV>(cp + k * G);
-  }
-  if constexpr (HAS_A) {
-#pragma unroll
-    for (int f = 0; f < MF; ++f) {
-      if (f < A.m && A.a_slot[f] >= 0) {
-        const TV* ap = reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + m.s + lid;
-        DL_FOR_K(k, KMAX, K) R.a[f][k] = ldv<TV>(ap + k * G);
-      }
-    }
-  }
-}
-
-// v = (c + sum_k a_k mu_k[j]) * (-1/gamma) in place of c; -inf past the row end.
-template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
-                                         RowRegs<MF, HAS_A, KMAX>& R, const float* s_mu,
-                                         float (&cc)[(MODE & M_REPAIR) ? KMAX : 1]) {
-  constexpr int G = 1 << GLOG;
-  K = __builtin_amdgcn_readfirstlane(K);
-  const int d = (int)(m.e - m.s);
-  DL_FOR_KC(k, KMAX, K) {
-    {
-      const bool in = lid + k * G < d;
-      float val;
-      if constexpr ((MODE & M_VIN) != 0) {
-        val = R.c[k];
-      } else {
-        const int j = R.j[k];
-        float sdot = 0.f;
-#pragma unroll
-        for (int f = 0; f < MF; ++f) {
-          if (f < A.m) {
-            float af = 1.f;
-            if constexpr (HAS_A) {
-              if (A.a_slot[f] >= 0) af = R.a[f][k];
-            }
-            sdot = fmaf(af, s_mu[f * A.J + j], sdot);
-          }
-        }
-        if constexpr ((MODE & M_REPAIR) != 0) cc[k] = R.c[k];
-        val = (R.c[k] + sdot) * A.neg_inv_gamma;  // eq. 3 argument
-      }
-      R.c[k] = in ? val : -INFINITY;
-    }
-  }
-}
-
-// Box-cut set {0 <= x <= u, sum x <= z} (Table 1's third projection kind):
-// x = clamp(v - theta, 0, u), theta = 0 when clamp(v, 0, u) sums to at most
-// z, else the root of f(theta) = sum clamp(v - theta, 0, u) - z, which is
-// nonincreasing and linear between the breakpoints {v, v - u}.  Evaluation at
-// theta: f, the count of coordinates free just right of theta (0 < v - theta
-// <= u: one sitting at its cap starts to move) and the next breakpoint above
-// theta.
-template <int GLOG, int KMAX, bool HAS_A>
-__device__ __forceinline__ void boxcut_eval(const float (&v)[KMAX], int K, float theta, float u, float& f,
-                                            float& cnt, float& nb) {
-  f = 0.f;
-  cnt = 0.f;
-  nb = INFINITY;
-  DL_FOR_KC(k, KMAX, K) {
-    {
-      const float t = v[k] - theta;
-      f += fminf(fmaxf(t, 0.f), u);
-      cnt += (t > 0.f && t <= u) ? 1.f : 0.f;
-      nb = fminf(nb, t > u ? v[k] - u : (t > 0.f ? v[k] : INFINITY));
-    }
-  }
-  f = gsum<GLOG>(f);
-  cnt = gsum<GLOG>(cnt);
-  nb = gmin<GLOG>(nb);
-}
-
-// theta of every lane group of the wavefront: Newton steps from the left end
-// of a bracket [lo, hi] (exact once the step stays inside the piece that
-// starts at lo), the secant of the bracket once no breakpoint lies inside it
-// (exact as well), bisection otherwise.  Every lane runs every round (the
-// group reductions need the whole wavefront).
-template <int GLOG, int KMAX, bool HAS_A>
-__device__ __forceinline__ float boxcut_theta(const float (&v)[KMAX], int K, float z, float u) {
-  float flo, clo, nblo;
-  boxcut_eval<GLOG, KMAX, HAS_A>(v, K, 0.f, u, flo, clo, nblo);
-  flo -= z;
-  float m1 = -INFINITY;
-  DL_FOR_KC(k, KMAX, K) m1 = fmaxf(m1, v[k]);
-  m1 = gmax<GLOG>(m1);
-  bool done = !(flo > 0.f);  // clamp(v, 0, u) already fits (or no user here)
-  float theta = 0.f, lo = 0.f, hi = m1, fhi = -z;
-  for (int it = 0; it < 64 && __any(!done); ++it) {
-    float cand = 0.5f * (lo + hi);
-    if (!done) {
-      if (clo > 0.f) {
-        const float tn = lo + flo * __builtin_amdgcn_rcpf(clo);
-        if (tn <= nblo) {
-          theta = tn;  // the linear piece at lo reaches z: exact
-          done = true;
-        }
-        cand = tn;
-      } else {
-        cand = nblo;
-      }
-      if (!done && nblo >= hi) {
-        theta = lo + (hi - lo) * (flo / (flo - fhi));  // f is linear on [lo, hi]
-        done = true;
-      }
-      if (!(cand > lo && cand < hi)) cand = 0.5f * (lo + hi);
-    }
-    float f, c, nb;
-    boxcut_eval<GLOG, KMAX, HAS_A>(v, K, cand, u, f, c, nb);
-    f -= z;
-    if (!done) {
-      if (fabsf(f) <= z * 0x1p-22f) {
-        theta = cand;
-        done = true;
-      } else if (f > 0.f) {
-        lo = cand;
-        flo = f;
-        clo = c;
-        nblo = nb;
-      } else {
-        hi = cand;
-        fhi = f;
-      }
-    }
-  }
-  if (!done) theta = clo > 0.f ? lo + flo / clo : lo;
-  return theta;
-}
-
-// Projects the task's rows (v in R.c) and accumulates what MODE asks.
-template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
-                                             RowRegs<MF, HAS_A, KMAX>& R, const float* s_rf,
-                                             unsigned long long* s_hist, double& acc,
-                                             const float (&cc)[(MODE & M_REPAIR) ? KMAX : 1],
-                                             const float (&qs)[DL_MAX_FAMILIES]) {
-  constexpr int G = 1 << GLOG;
-  K = __builtin_amdgcn_readfirstlane(K);
-  float (&v)[KMAX] = R.c;
-  const float z = A.radius;
-  const bool box = (A.proj == DL_PROJ_BOX);
-  const bool boxcut = (A.proj == DL_PROJ_BOXCUT);
-  float theta = 0.f;
-  if (boxcut) {
-    theta = boxcut_theta<GLOG, KMAX, HAS_A>(v, K, z, A.upper);
-  } else if (!box) {
-    // pass A: largest two entries, positive part and its count
-    float m1 = -INFINITY, m2 = -INFINITY, sp = 0.f, cp = 0.f;
-    DL_FOR_KC(k, KMAX, K) {
-      {
-        m2 = fmaxf(m2, fminf(m1, v[k]));
-        m1 = fmaxf(m1, v[k]);
-        sp += fmaxf(v[k], 0.f);
-        cp += v[k] > 0.f ? 1.f : 0.f;
-      }
-    }
-    gtop2<GLOG>(m1, m2);
-    sp = gsum<GLOG>(sp);
-    cp = gsum<GLOG>(cp);
-    const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
-    bool done;
-    if (m1 == -INFINITY || (!eq && sp <= z)) {
-      done = true;                       // no user here, or the positive part already fits
-    } else if (m1 - m2 >= z) {
-      theta = m1 - z;                    // the leader alone carries mass z
-      done = true;
-    } else {
-      theta = m1 - z;                    // f(m1 - z) >= 0: left of the root
-      if (sp > z) theta = fmaxf(theta, (sp - z) * __builtin_amdgcn_rcpf(cp));  // Newton step from 0
-      done = false;
-    }
-    for (int it = 0; it < 64 && __any(!done); ++it) {
-      float f = 0.f, cnt = 0.f, mina = INFINITY;
-      DL_FOR_KC(k, KMAX, K) {
-        {
-          const float t = v[k] - theta;
-          f += fmaxf(t, 0.f);
-          const bool act = t > 0.f;
-          cnt += act ? 1.f : 0.f;
-          mina = fminf(mina, act ? v[k] : INFINITY);
-        }
-      }
-      f = gsum<GLOG>(f);
-      cnt = gsum<GLOG>(cnt);
-      mina = gmin<GLOG>(mina);
-      if (!done) {
-        // Newton step: the exact threshold of the active set {v > theta}; the
-        // set survives the step when its smallest member stays above it
-        const float nt = theta + (f - z) * __builtin_amdgcn_rcpf(cnt);
-        done = (mina > nt) || (fabsf(f - z) <= z * 0x1p-22f);
-        theta = nt;
-      }
-    }
-  }
-
-  float lobj = 0.f;
-  auto emit = [&](int k, float x) {
-    {
-      if constexpr ((MODE & M_XOUT) != 0) {
-        if (lid + k * G < (int)(m.e - m.s)) A.x_out[m.os + lid + k * G] = x;
-      }
-      if constexpr ((MODE & M_HIST) != 0) {
-#pragma unroll
-        for (int f = 0; f < MF; ++f) {
-          if (f < A.m) {
-            float w = x;
-            if constexpr (HAS_A) {
-              if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
-            }
-            if constexpr (HAS_A) hist_add(s_hist, f * A.J + R.j[k], w, qs[f]);
-            else hist_add_pos(s_hist, f * A.J + R.j[k], w, qs[f]);
-          }
-        }
-      }
-      if constexpr ((MODE & M_OBJ) != 0) {
-        // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
-        // (padding lanes hold v = -inf, whose term must not be formed)
-        const float term = x * fmaf(0.5f * A.gamma, x, -A.gamma * v[k]);
-        lobj += x > 0.f ? term : 0.f;
-      }
-      if constexpr ((MODE & M_REPAIR) != 0) {
-        const float xt = s_rf[R.j[k]] * x;
-        lobj += xt * fmaf(0.5f * A.gamma, xt, cc[k]);
-      }
-    }
-  };
-  // one loop per projection kind, so the kind is not re-tested per element
-  if (box) {
-    DL_FOR_KC(k, KMAX, K) emit(k, fminf(fmaxf(v[k], 0.f), z));
-  } else if (boxcut) {
-    const float u = A.upper;
-    DL_FOR_KC(k, KMAX, K) emit(k, fminf(fmaxf(v[k] - theta, 0.f), u));
-  } else {
-    DL_FOR_KC(k, KMAX, K) emit(k, fmaxf(v[k] - theta, 0.f));
-  }
-  if (MODE & (M_OBJ | M_REPAIR)) acc += (double)lobj;
-}
-
-// The tasks t0, t0 + DL_WAVES, ... < t1 of one bucket.  With PF the next
-// task's rows load while the current one is projected: gather (waits for this
-// task's rows), issue the next task's loads, then project and accumulate.
-template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucket& B, int64_t t0, int64_t t1,
-                                           int lane, const float* s_mu, const float* s_rf,
-                                           unsigned long long* s_hist, double& acc,
-                                           const float (&qs)[DL_MAX_FAMILIES]) {
-  if (t0 >= t1) return;
-  // keeps per-bucket lane arithmetic inside this bucket's code (otherwise it is
-  // hoisted out of the kernel's bucket loop for every bucket at once and spills)
-  asm volatile("" : "+v"(lane));
-  constexpr bool PF = (MF == 1) && !(MODE & M_REPAIR);
-  constexpr int G = 1 << GLOG;
-  const int lid = lane & (G - 1);
-  constexpr bool need_os = (MODE & (M_VIN | M_XOUT)) != 0;
-  auto kof = [&](const TaskMeta& m) {
-    // users are sorted longest first: lane 0 holds the task's longest row
-    const int d0 = __builtin_amdgcn_readfirstlane((int)(m.e - m.s));
-    return (d0 + G - 1) >> GLOG;
-  };
-  float cc[(MODE & M_REPAIR) ? KMAX : 1];
-  if constexpr (!PF) {
-    RowRegs<MF, HAS_A, KMAX> R;
-    for (int64_t t = t0; t < t1; t += DL_WAVES) {
-      TaskMeta m = load_meta<GLOG>(A, B, t, lane, need_os);
-      const int K = kof(m);
-      load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R);
-      gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R, s_mu, cc);
-      project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, m, K, lid, R, s_rf, s_hist, acc, cc, qs);
-    }
-    return;
-  }
-  RowRegs<MF, HAS_A, KMAX> RA, RB;
-  TaskMeta ma = load_meta<GLOG>(A, B, t0, lane, need_os);
-  TaskMeta mb = ma;
-  int64_t t = t0;
-  if (t + DL_WAVES < t1) mb = load_meta<GLOG>(A, B, t + DL_WAVES, lane, need_os);
-  int ka = kof(ma), kb = 0;
-  load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA);
-  while (true) {
-    gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA, s_mu, cc);
-    TaskMeta mc = mb;
-    if (t + DL_WAVES < t1) {
-      kb = kof(mb);
-      load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB);
-      if (t + 2 * DL_WAVES < t1) mc = load_meta<GLOG>(A, B, t + 2 * DL_WAVES, lane, need_os);
-    }
-    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, ma, ka, lid, RA, s_rf, s_hist, acc, cc, qs);
-    t += DL_WAVES;
-    if (t >= t1) break;
-    gather_v<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB, s_mu, cc);
-    TaskMeta md = mc;
-    if (t + DL_WAVES < t1) {
-      ka = kof(mc);
-      load_rows<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mc, ka, lid, RA);
-      if (t + 2 * DL_WAVES < t1) md = load_meta<GLOG>(A, B, t + 2 * DL_WAVES, lane, need_os);
-    }
-    project_task<GLOG, MF, HAS_A, KMAX, TV, MODE>(A, mb, kb, lid, RB, s_rf, s_hist, acc, cc, qs);
-    t += DL_WAVES;
-    if (t >= t1) break;
-    ma = mc;
-    mb = md;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Rows longer than 64*KMAX: one wavefront per user, re-reading the row per
-// Newton step (the row stays in L1/L2, so HBM sees it once).
-// ---------------------------------------------------------------------------
-template <int MF, bool HAS_A, typename TV, int MODE>
-__device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu, int64_t s, int64_t os, int e,
-                                        int& j, float& c, float (&af)[HAS_A ? MF : 1]) {
-  if constexpr ((MODE & M_VIN) != 0) return A.v_in[os + e];
-  j = A.idx[s + e];
-  c = ldv<TV>(reinterpret_cast<const TV*>(A.cval) + s + e);
-  float sdot = 0.f;
-#pragma unroll
-  for (int f = 0; f < MF; ++f) {
-    if (f < A.m) {
-      float a = 1.f;
-      if (HAS_A && A.a_slot[f] >= 0)
-        a = ldv<TV>(reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + s + e);
-      if (HAS_A) af[f] = a;
-      sdot = fmaf(a, s_mu[f * A.J + j], sdot);
-    }
-  }
-  return (c + sdot) * A.neg_inv_gamma;
-}
-
-template <int MF, bool HAS_A, typename TV, int MODE>
-__device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, const dl_bucket& B, const float* s_mu,
-                                          const float* s_rf, unsigned long long* s_hist, int lane, double& acc,
-                                          const float (&qs)[DL_MAX_FAMILIES]) {
-  const int64_t u = B.user_begin + (t - B.task_begin);
-  const int64_t s = A.rp[u];
-  const int d = (int)(A.rp[u + 1] - s);
-  const int64_t os = (MODE & (M_VIN | M_XOUT)) ? A.orig_rp[u] : 0;
-  const float z = A.radius;
-  const bool box = (A.proj == DL_PROJ_BOX);
-  const bool boxcut = (A.proj == DL_PROJ_BOXCUT);
-  const float ucap = A.upper;
-  int j = 0;
-  float c = 0.f;
-  float af[HAS_A ? MF : 1];
-  float theta = 0.f;
-  if (boxcut) {
-    // same bracketed Newton iteration as the group path, one wavefront per row
-    auto eval = [&](float th, float& f, float& cnt, float& nb) {
-      f = 0.f;
-      cnt = 0.f;
-      nb = INFINITY;
-      for (int e = lane; e < d; e += 64) {
-        const float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
-        const float t = v - th;
-        f += fminf(fmaxf(t, 0.f), ucap);
-        cnt += (t > 0.f && t <= ucap) ? 1.f : 0.f;
-        nb = fminf(nb, t > ucap ? v - ucap : (t > 0.f ? v : INFINITY));
-      }
-      f = gsum<6>(f);
-      cnt = gsum<6>(cnt);
-      nb = gmin<6>(nb);
-    };
-    float flo, clo, nblo;
-    eval(0.f, flo, clo, nblo);
-    flo -= z;
-    if (flo > 0.f) {
-      float vmax = -INFINITY;
-      for (int e = lane; e < d; e += 64) vmax = fmaxf(vmax, long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af));
-      float lo = 0.f, hi = gmax<6>(vmax), fhi = -z;
-      bool done = false;
-      for (int it = 0; it < 64 && !done; ++it) {
-        float cand;
-        if (clo > 0.f) {
-          cand = lo + flo / clo;
-          if (cand <= nblo) {
-            theta = cand;
-            done = true;
-            break;
-          }
-        } else {
-          cand = nblo;
-        }
-        if (nblo >= hi) {
-          theta = lo + (hi - lo) * (flo / (flo - fhi));  // f is linear on [lo, hi]
-          done = true;
-          break;
-        }
-        if (!(cand > lo && cand < hi)) cand = 0.5f * (lo + hi);
-        float f, cn, nb;
-        eval(cand, f, cn, nb);
-        f -= z;
-        if (fabsf(f) <= z * 0x1p-22f) {
-          theta = cand;
-          done = true;
-        } else if (f > 0.f) {
-          lo = cand;
-          flo = f;
-          clo = cn;
-          nblo = nb;
-        } else {
-          hi = cand;
-          fhi = f;
-        }
-      }
-      if (!done) theta = clo > 0.f ? lo + flo / clo : lo;
-    }
-  } else if (!box) {
-    float vmax = -INFINITY, sp = 0.f, cp = 0.f;
-    for (int e = lane; e < d; e += 64) {
-      float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
-      vmax = fmaxf(vmax, v);
-      sp += fmaxf(v, 0.f);
-      cp += v > 0.f ? 1.f : 0.f;
-    }
-    vmax = gmax<6>(vmax);
-    sp = gsum<6>(sp);
-    cp = gsum<6>(cp);
-    const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
-    if (eq || sp > z) {
-      theta = vmax - z;
-      if (sp > z && cp > 0.f) theta = fmaxf(theta, (sp - z) / cp);
-      for (int it = 0; it < 64; ++it) {
-        float f = 0.f, cnt = 0.f, mina = INFINITY;
-        for (int e = lane; e < d; e += 64) {
-          float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
-          float tt = v - theta;
-          f += fmaxf(tt, 0.f);
-          cnt += tt > 0.f ? 1.f : 0.f;
-          mina = fminf(mina, tt > 0.f ? v : INFINITY);
-        }
-        f = gsum<6>(f);
-        cnt = gsum<6>(cnt);
-        mina = gmin<6>(mina);
-        const float nt = theta + (f - z) / cnt;
-        const bool stable = (mina > nt) || (fabsf(f - z) <= z * 0x1p-22f);
-        theta = nt;
-        if (stable) break;
-      }
-    }
-  }
-  float lobj = 0.f;
-  for (int e = lane; e < d; e += 64) {
-    float v = long_v<MF, HAS_A, TV, MODE>(A, s_mu, s, os, e, j, c, af);
-    float x = box ? fminf(fmaxf(v, 0.f), z) : (boxcut ? fminf(fmaxf(v - theta, 0.f), ucap) : fmaxf(v - theta, 0.f));
-    if constexpr ((MODE & M_XOUT) != 0) A.x_out[os + e] = x;
-    if constexpr ((MODE & M_HIST) != 0) {
-#pragma unroll
-      for (int f = 0; f < MF; ++f) {
-        if (f < A.m) {
-          float w = (HAS_A && A.a_slot[f] >= 0) ? af[HAS_A ? f : 0] * x : x;
-          if constexpr (HAS_A) hist_add(s_hist, f * A.J + j, w, qs[f]);
-          else hist_add_pos(s_hist, f * A.J + j, w, qs[f]);
-        }
-      }
-    }
-    if constexpr ((MODE & M_OBJ) != 0) lobj += x > 0.f ? x * fmaf(0.5f * A.gamma, x, -A.gamma * v) : 0.f;
-    if constexpr ((MODE & M_REPAIR) != 0) {
-      const float xt = s_rf[j] * x;
-      lobj += xt * fmaf(0.5f * A.gamma, xt, c);
-    }
-  }
-  if (MODE & (M_OBJ | M_REPAIR)) acc += (double)lobj;
-}
-
-// One workgroup's share of a pass: tasks [w0, w1) of the instance A describes;
-// its histogram goes to partial slot `slot`.
-template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int64_t w1, int slot) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int mJ = A.m * A.J;
-  const bool need_mu = !(MODE & M_VIN);
-  float* s_mu = reinterpret_cast<float*>(smem);
-  const int mu_n = need_mu ? mJ : 0;
-  float* s_rf = s_mu + mu_n;
-  const int rf_n = (MODE & M_REPAIR) ? A.J : 0;
-  size_t off = ((size_t)(mu_n + rf_n) * 4 + 15) & ~(size_t)15;
-  unsigned long long* s_hist = reinterpret_cast<unsigned long long*>(smem + off);
-  const int hist_n = (MODE & M_HIST) ? mJ : 0;
-  double* s_obj = reinterpret_cast<double*>(smem + off + (size_t)hist_n * 8);
-
-  const int tid = threadIdx.x;
-  unsigned long long t_start = 0;
-  if (A.wg_clock && tid == 0) t_start = (unsigned long long)wall_clock64();
-  for (int r = tid; r < mu_n; r += DL_WG) s_mu[r] = A.mu[r];
-  for (int r = tid; r < rf_n; r += DL_WG) s_rf[r] = A.rfac[r];
-  for (int r = tid; r < hist_n; r += DL_WG) s_hist[r] = 0ull;
-  __syncthreads();
-
-  const int wave = tid >> 6;
-  const int lane = tid & 63;
-  double acc = 0.0;
-  // this pass's fixed-point scales (uniform)
-  float qs[DL_MAX_FAMILIES];
-#pragma unroll
-  for (int f = 0; f < DL_MAX_FAMILIES; ++f)
-    qs[f] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.qs_dev ? A.qs_dev[f] : A.qscale[f])));
-  for (int b = 0; b < A.n_buckets; ++b) {
-    const dl_bucket& B = A.bk[b];
-    const int64_t b1 = (b + 1 < A.n_buckets) ? A.bk[b + 1].task_begin : w1;
-    const int64_t lo = w0 > B.task_begin ? w0 : B.task_begin;
-    const int64_t hi = w1 < b1 ? w1 : b1;
-    if (lo >= hi) continue;
-    // this wavefront's tasks: w0 + wave + k*DL_WAVES inside [lo, hi)
-    int64_t first = w0 + wave;
-    if (first < lo) first += ((lo - first + DL_WAVES - 1) / DL_WAVES) * DL_WAVES;
-    switch (B.glog) {
-      case 0: run_bucket<0, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
-      case 1: run_bucket<1, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
-      case 2: run_bucket<2, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
-      case 3: run_bucket<3, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
-      case 4: run_bucket<4, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
-      case 5: run_bucket<5, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
-      case 6: run_bucket<6, MF, HAS_A, KMAX, TV, MODE>(A, B, first, hi, lane, s_mu, s_rf, s_hist, acc, qs); break;
-      default:
-        for (int64_t t = first; t < hi; t += DL_WAVES)
-          long_task<MF, HAS_A, TV, MODE>(A, t, B, s_mu, s_rf, s_hist, lane, acc, qs);
-        break;
-    }
-  }
-  if (MODE & (M_OBJ | M_REPAIR)) {
-    // fixed-order FP64 reduction: lanes of a wavefront, then wavefronts in order
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) s_obj[wave] = acc;
-  }
-  __syncthreads();
-  if (MODE & M_HIST) {
-    unsigned long long* dst = A.part + (size_t)slot * mJ;
-    for (int r = tid; r < mJ; r += DL_WG) dst[r] = s_hist[r];
-  }
-  if ((MODE & (M_OBJ | M_REPAIR)) && tid == 0) {
-    double tot = 0.0;
-    for (int w = 0; w < DL_WAVES; ++w) tot += s_obj[w];
-    A.obj_part[slot] = tot;
-  }
-  if (A.wg_clock) {
-    __syncthreads();
-    if (tid == 0) {
-      A.wg_clock[2 * slot] = t_start;
-      A.wg_clock[2 * slot + 1] = (unsigned long long)wall_clock64();
-    }
-  }
-}
-
-template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__global__ void __launch_bounds__(DL_WG) grad_pass(dl_grad_args A) {
-  grad_body<MF, HAS_A, KMAX, TV, MODE>(A, A.wg_task[blockIdx.x], A.wg_task[blockIdx.x + 1], (int)blockIdx.x);
-}
-
-// Many instances in one launch: workgroup w serves tasks [t0, t1) of
-// instance wgs[w].inst (per-instance arguments in device memory).
-template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-__global__ void __launch_bounds__(DL_WG) grad_pass_batch(const dl_grad_args* __restrict__ args,
-                                                         const dl_wg_desc* __restrict__ wgs) {
-  const dl_wg_desc w = wgs[blockIdx.x];
-  grad_body<MF, HAS_A, KMAX, TV, MODE>(args[w.inst], w.t0, w.t1, w.slot);
-}
-
-template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
-dl_status launch_one(const dl_problem* P, const dl_grad_args& A, size_t lds) {
-  hipLaunchKernelGGL((grad_pass<MF, HAS_A, KMAX, TV, MODE>), dim3(P->n_wg), dim3(DL_WG), lds, P->stream, A);
-  DL_HIP_TRY(hipGetLastError());
-  return DL_OK;
-}
-
-template <int MF, bool HAS_A, int KMAX, typename TV>
-dl_status launch_mode(const dl_problem* P, int mode, const dl_grad_args& A, size_t lds) {
-  switch (mode) {
-    case M_HIST: return launch_one<MF, HAS_A, KMAX, TV, M_HIST>(P, A, lds);
-    case M_HIST | M_OBJ: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ>(P, A, lds);
-    case M_HIST | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT>(P, A, lds);
-    case M_HIST | M_OBJ | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT>(P, A, lds);
-    case M_REPAIR: return launch_one<MF, HAS_A, KMAX, TV, M_REPAIR>(P, A, lds);
-    case M_VIN | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_VIN | M_XOUT>(P, A, lds);
-    default: dl_set_error("internal: unknown gradient-pass mode"); return DL_EINVAL;
-  }
-}
-
-template <int MF, bool HAS_A, int KMAX>
-dl_status launch_storage(const dl_problem* P, int mode, const dl_grad_args& A, size_t lds) {
-  if (P->storage == DL_BF16) return launch_mode<MF, HAS_A, KMAX, uint16_t>(P, mode, A, lds);
-  return launch_mode<MF, HAS_A, KMAX, float>(P, mode, A, lds);
-}
-
-template <int MF, bool HAS_A, int KMAX, typename TV>
-dl_status launch_batch_t(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
-                         size_t lds, hipStream_t st) {
-  (void)P;
-  hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST>), dim3(n_wg), dim3(DL_WG), lds, st, d_args, d_wgs);
-  DL_HIP_TRY(hipGetLastError());
-  return DL_OK;
-}
-
-template <int MF, bool HAS_A, int KMAX, typename TV>
-void set_attr_all() {
-  (void)hipFuncSetAttribute((const void*)grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  const int big = 160 * 1024;
-  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_REPAIR>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
-}
 
 // Fixed-point scale of each family for one histogram pass.  For every item j
 // and user i, with a of any sign and lam of any sign:
@@ -903,14 +150,14 @@ size_t dl_grad_lds_bytes(const dl_problem* P, int mode) {
 
 dl_status dl_grad_prepare(const dl_problem* P) {
   if (P->mf == 1 && !P->has_a) {
-    set_attr_all<1, false, DL_KMAX_PLAIN, float>();
-    set_attr_all<1, false, DL_KMAX_PLAIN, uint16_t>();
+    dl_grad_attr_v_1_0_0();
+    dl_grad_attr_v_1_0_1();
   } else if (P->mf == 1) {
-    set_attr_all<1, true, DL_KMAX_A, float>();
-    set_attr_all<1, true, DL_KMAX_A, uint16_t>();
+    dl_grad_attr_v_1_1_0();
+    dl_grad_attr_v_1_1_1();
   } else {
-    set_attr_all<4, true, DL_KMAX_A, float>();
-    set_attr_all<4, true, DL_KMAX_A, uint16_t>();
+    dl_grad_attr_v_4_1_0();
+    dl_grad_attr_v_4_1_1();
   }
   return DL_OK;
 }
@@ -920,13 +167,13 @@ dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args
   if (n_wg <= 0) return DL_OK;
   const bool bf = P->storage == DL_BF16;
   if (P->mf == 1 && !P->has_a)
-    return bf ? launch_batch_t<1, false, DL_KMAX_PLAIN, uint16_t>(P, n_wg, d_args, d_wgs, lds, st)
-              : launch_batch_t<1, false, DL_KMAX_PLAIN, float>(P, n_wg, d_args, d_wgs, lds, st);
+    return bf ? dl_grad_batch_v_1_0_1(P, n_wg, d_args, d_wgs, lds, st)
+              : dl_grad_batch_v_1_0_0(P, n_wg, d_args, d_wgs, lds, st);
   if (P->mf == 1)
-    return bf ? launch_batch_t<1, true, DL_KMAX_A, uint16_t>(P, n_wg, d_args, d_wgs, lds, st)
-              : launch_batch_t<1, true, DL_KMAX_A, float>(P, n_wg, d_args, d_wgs, lds, st);
-  return bf ? launch_batch_t<4, true, DL_KMAX_A, uint16_t>(P, n_wg, d_args, d_wgs, lds, st)
-            : launch_batch_t<4, true, DL_KMAX_A, float>(P, n_wg, d_args, d_wgs, lds, st);
+    return bf ? dl_grad_batch_v_1_1_1(P, n_wg, d_args, d_wgs, lds, st)
+              : dl_grad_batch_v_1_1_0(P, n_wg, d_args, d_wgs, lds, st);
+  return bf ? dl_grad_batch_v_4_1_1(P, n_wg, d_args, d_wgs, lds, st)
+            : dl_grad_batch_v_4_1_0(P, n_wg, d_args, d_wgs, lds, st);
 }
 
 dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamma) {
@@ -972,7 +219,9 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
   A.obj_part = obj_part;
   A.x_out = x_out;
   const size_t lds = dl_grad_lds_bytes(P, mode);
-  if (P->mf == 1 && !P->has_a) return launch_storage<1, false, DL_KMAX_PLAIN>(P, mode, A, lds);
-  if (P->mf == 1) return launch_storage<1, true, DL_KMAX_A>(P, mode, A, lds);
-  return launch_storage<4, true, DL_KMAX_A>(P, mode, A, lds);
+  const bool bf = P->storage == DL_BF16;
+  if (P->mf == 1 && !P->has_a)
+    return bf ? dl_grad_launch_v_1_0_1(P, mode, A, lds) : dl_grad_launch_v_1_0_0(P, mode, A, lds);
+  if (P->mf == 1) return bf ? dl_grad_launch_v_1_1_1(P, mode, A, lds) : dl_grad_launch_v_1_1_0(P, mode, A, lds);
+  return bf ? dl_grad_launch_v_4_1_1(P, mode, A, lds) : dl_grad_launch_v_4_1_0(P, mode, A, lds);
 }
