@@ -258,8 +258,24 @@ def solve(inst, gammas: Sequence[float], iters: Sequence[int], tol: float = 1e-4
 
 
 def bf16_round(x: np.ndarray) -> np.ndarray:
-    """Round-to-nearest-even of FP32 values to BF16, returned as FP32."""
-    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    lsb = (u >> 16) & 1
-    r = ((u + 0x7FFF + lsb) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
+    """Round-to-nearest-even of FP32 values to BF16 (8 significant bits, FP32's
+    exponent range), returned as FP32.
+
+    Written from the definition of the format rather than its bit layout: a
+    finite x is a multiple of the quantum q = 2^(max(e, -126) - 7), with e the
+    exponent of its leading bit (-126 is the smallest normal exponent, below it
+    the quantum stays 2^-133); x / q is exact in FP64, rounded to the nearest
+    integer with ties to even, and scaled back.  A result of magnitude 2^128 or
+    more is outside the format and becomes +-inf; NaN and +-inf pass through.
+    """
+    with np.errstate(invalid="ignore", over="ignore"):  # NaN payloads and overflow to inf
+        x32 = np.ascontiguousarray(x, dtype=np.float32)
+        xd = x32.astype(np.float64)
+        out = xd.copy()
+        fin = np.isfinite(xd) & (xd != 0.0)
+        _, E = np.frexp(xd[fin])                      # |x| = f 2^E with f in [0.5, 1)
+        q = np.ldexp(1.0, np.maximum(E - 1, -126) - 7)
+        r = np.rint(xd[fin] / q) * q                  # rint: nearest, ties to even
+        r = np.where(np.abs(r) >= 2.0 ** 128, np.copysign(np.inf, r), r)
+        out[fin] = r
+        return out.astype(np.float32)
