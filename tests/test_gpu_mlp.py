@@ -157,3 +157,45 @@ def test_input_norm_and_predicted_duals(dl, orc):
     # same network output as forward; the FP64 epilogue may fuse the multiply-add
     np.testing.assert_allclose(lam0, np.maximum(0.0, lam_prev + s * y.astype(np.float64)), rtol=1e-15, atol=1e-17)
     assert (lam0 >= 0).all() and (lam0 == 0).any() and (lam0 > 0).any()
+
+
+def test_adamw_steps_match_oracle(dl, orc):
+    """Five dl_mlp_train_step calls (nonzero weight decay) against the oracle's
+    AdamW fed the same gradients.  Each step's gradient is the GPU's own: the
+    loss gradient dy = (y - t) / n is formed in FP32 exactly as the kernel forms
+    it and passed to dl_mlp_gradients, which runs the kernels the training step
+    runs.  The oracle keeps FP64 parameters and moments; the GPU keeps FP32, so
+    after s steps the parameters differ by at most s FP32 roundings of each
+    parameter and of each update (a few ulp of lr), far below one step's size."""
+    import torch
+    from oracle import mlp as om
+    hidden, n = 256, 2000
+    lr, wd = 1e-3, 1e-2
+    p0 = om.init_params(5, hidden=hidden)
+    p0["b1"] = np.random.default_rng(6).normal(size=hidden) * 0.05
+    flat0 = om.flatten(p0).astype(np.float32)
+    net = dl.MLP(hidden=hidden, max_batch=n)
+    net.set_params(flat0)
+    rng = np.random.default_rng(8)
+    X = np.zeros((n, 16), dtype=np.float32)
+    X[:, :12] = rng.normal(size=(n, 12)).astype(np.float32)
+    t = rng.normal(size=n).astype(np.float32)
+    Xt, tt = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    po = om.unflatten(flat0.astype(np.float64), hidden=hidden)
+    mo = {k: np.zeros_like(v) for k, v in po.items()}
+    vo = {k: np.zeros_like(v) for k, v in po.items()}
+    for step in range(1, 6):
+        y = net.forward(Xt).cpu().numpy()
+        dy = ((y - t).astype(np.float32) / np.float32(n)).astype(np.float32)
+        _, g = net.gradients(Xt, torch.from_numpy(dy).cuda())
+        go = om.unflatten(g.cpu().numpy().astype(np.float64), hidden=hidden)
+        po = om.adamw_step(po, go, mo, vo, step, lr, wd=wd)
+        net.train_step(Xt, tt, lr, wd)
+        pg = net.get_params().astype(np.float64)
+        ref = om.flatten(po)
+        err = np.abs(pg - ref)
+        tol = step * (2.0 ** -23 * np.abs(ref) + 1e-5 * lr)
+        moved = np.abs(ref - flat0.astype(np.float64))
+        print(f"step {step}: max |p_gpu - p_oracle| {err.max():.2e}, max move {moved.max():.2e}, "
+              f"worst err/tol {(err / tol).max():.3f}")
+        assert np.all(err <= tol), (step, float((err / tol).max()))
