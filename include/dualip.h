@@ -203,6 +203,26 @@ typedef struct {
 dl_status dl_solve(dl_problem* prob, const dl_solve_opts* opts, const double* lambda0,
                    double* lambda_out, dl_solve_stats* stats);
 
+/*
+ * dl_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same schedule, stopping rule, results and statuses as dl_solve, bitwise,
+ * but the solver state (lam', y', A x in FP64 and the two FP32 gather points:
+ * 32 bytes per coupling row, plus a flag) lives in one fixed device array of
+ * the library (524,544 bytes per device, held until the process ends) instead of
+ * memory allocated per call.  The problem's own buffers, made at create time,
+ * are used as by dl_solve; the call itself calls no hipMalloc or hipFree.
+ *   Limits  n_families * n_items <= 16384 (else DL_EUNSUPPORTED);
+ *           opts->autotune_rounds must be 0 (the tuner allocates; DL_EINVAL);
+ *           the problem's device must be the current device (DL_EINVAL).
+ *   Sharing every call on a device uses that device's one array and leaves
+ *           its contents behind (each call starts by setting what it reads):
+ *           calls that overlap on one device, from two threads or on two
+ *           streams, race and must be serialised by the caller.
+ */
+dl_status dl_solve_noalloc(dl_problem* prob, const dl_solve_opts* opts, const double* lambda0,
+                           double* lambda_out, dl_solve_stats* stats);
+
 /* Stepwise access to the same iteration, for trajectories and timing. */
 dl_status dl_solver_create(dl_problem* prob, const double* lambda0, dl_solver** out);
 void dl_solver_destroy(dl_solver* s);

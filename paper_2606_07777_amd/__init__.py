@@ -156,6 +156,7 @@ SIGNATURES = {
     "dl_dual_grad": ([_VP, _VP, _D, _VP, _VP, _VP], _I32),
     "dl_project": ([_VP, _VP, _VP], _I32),
     "dl_solve": ([_VP, ctypes.POINTER(dl_solve_opts), _VP, _VP, ctypes.POINTER(dl_solve_stats)], _I32),
+    "dl_solve_noalloc": ([_VP, ctypes.POINTER(dl_solve_opts), _VP, _VP, ctypes.POINTER(dl_solve_stats)], _I32),
     "dl_solver_create": ([_VP, _VP, ctypes.POINTER(_VP)], _I32),
     "dl_solver_destroy": ([_VP], None),
     "dl_solver_set_stage": ([_VP, _D, _D, _I32], _I32),
@@ -314,17 +315,24 @@ class Problem:
         return x
 
     def solve(self, gammas: Sequence[float], iters: Sequence[int], tol=1e-4, max_iters=20000, check_every=10,
-              reset_momentum=True, step_scale=1.0, lam0=None, autotune_rounds=0):
-        """dl_solve over the schedule; returns (lam tensor f64 [m*J], stats dict)."""
+              reset_momentum=True, step_scale=1.0, lam0=None, autotune_rounds=0, out=None, noalloc=False):
+        """dl_solve over the schedule; returns (lam tensor f64 [m*J], stats dict).
+
+        noalloc=True calls dl_solve_noalloc (no device allocation inside the call);
+        out may then be a preallocated float64 tensor of m*J entries."""
         torch = self.torch
         g = np.ascontiguousarray(gammas, dtype=np.float64)
         it = np.ascontiguousarray(iters, dtype=np.int64)
         o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
                           int(reset_momentum), int(autotune_rounds), float(step_scale))
         l0 = None if lam0 is None else lam0.to(device="cuda", dtype=torch.float64).contiguous()
-        out = self._empty(self.m * self.J, torch.float64)
+        if out is None:
+            out = self._empty(self.m * self.J, torch.float64)
+        elif out.dtype != torch.float64 or out.numel() != self.m * self.J or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of m*J entries")
         st = dl_solve_stats()
-        _check(load().dl_solve(self.handle, ctypes.byref(o), _ptr(l0), _ptr(out), ctypes.byref(st)),
+        fn = load().dl_solve_noalloc if noalloc else load().dl_solve
+        _check(fn(self.handle, ctypes.byref(o), _ptr(l0), _ptr(out), ctypes.byref(st)),
                allow=(DL_OK, DL_NOT_CONVERGED))
         return out, st.as_dict()
 

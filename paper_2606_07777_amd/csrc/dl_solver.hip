@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <utility>
 
 #include "dl_common.h"
@@ -671,20 +672,25 @@ extern "C" dl_status dl_solver_autotune(dl_solver* S, int32_t rounds, dl_tune_re
   return dl_set_partition(P, c.b);
 }
 
-extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const double* lambda0, double* lambda_out,
-                              dl_solve_stats* st) {
-  DL_CHECK_ARG(P && o && st && lambda_out, "NULL argument");
+namespace {
+
+dl_status check_schedule(const dl_solve_opts* o) {
   DL_CHECK_ARG(o->n_stages >= 1 && o->gammas && o->iters, "empty schedule");
   for (int s = 0; s < o->n_stages; ++s) {
     DL_CHECK_ARG(o->gammas[s] > 0.0 && isfinite(o->gammas[s]), "gamma must be positive and finite");
     DL_CHECK_ARG(o->iters[s] >= 0 || s == o->n_stages - 1, "only the last stage may run until tol");
   }
   DL_CHECK_ARG(o->max_iters >= 0 && o->check_every >= 0, "negative limits");
+  return DL_OK;
+}
+
+// The schedule of dl_solve on a solver already at its starting point; writes the
+// final lam (problem units) and the stats.  Allocates nothing itself (the
+// workgroup tuner, when asked for, creates timing events).
+dl_status run_schedule(dl_solver* S, const dl_solve_opts* o, double* lambda_out, dl_solve_stats* st,
+                       std::chrono::steady_clock::time_point t0) {
+  dl_problem* P = S->P;
   const double step_scale = o->step_scale > 0.0 ? o->step_scale : 1.0;
-  auto t0 = std::chrono::steady_clock::now();
-  memset(st, 0, sizeof(*st));
-  dl_solver* S = nullptr;
-  DL_TRY(dl_solver_create(P, lambda0, &S));
   dl_status rc = DL_OK;
   bool converged = false;
   int64_t n_checks = 0;
@@ -740,9 +746,112 @@ extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const doubl
   st->n_checks = n_checks;
   st->status = (rc == DL_OK) ? (converged ? DL_OK : DL_NOT_CONVERGED) : rc;
   st->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  dl_solver_destroy(S);
   if (rc != DL_OK) return rc;
   return converged ? DL_OK : DL_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" dl_status dl_solve(dl_problem* P, const dl_solve_opts* o, const double* lambda0, double* lambda_out,
+                              dl_solve_stats* st) {
+  DL_CHECK_ARG(P && o && st && lambda_out, "NULL argument");
+  DL_TRY(check_schedule(o));
+  auto t0 = std::chrono::steady_clock::now();
+  memset(st, 0, sizeof(*st));
+  dl_solver* S = nullptr;
+  DL_TRY(dl_solver_create(P, lambda0, &S));
+  const dl_status rc = run_schedule(S, o, lambda_out, st, t0);
+  dl_solver_destroy(S);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// dl_solve without allocation: the solver state lives in a fixed device array
+// ---------------------------------------------------------------------------
+namespace {
+
+// Rows (m*J) the array holds: lam', y' and A x in FP64, the two FP32 gather
+// points, i.e. 32 bytes per row, plus the divergence flag.
+constexpr int64_t DL_NOALLOC_MAX_MJ = 16384;
+constexpr size_t DL_NOALLOC_BYTES = 32 * (size_t)DL_NOALLOC_MAX_MJ + 256;
+__device__ __align__(256) unsigned char scratch[DL_NOALLOC_BYTES];
+
+// Device address of `scratch` on each device (the host-side symbol is not one).
+constexpr int DL_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[DL_MAX_DEVICES] = {};
+
+__global__ void fill_i32(int* p, int n, int v) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) p[r] = v;
+}
+
+dl_status scratch_on_device(int dev, unsigned char** out) {
+  DL_CHECK_ARG(dev >= 0 && dev < DL_MAX_DEVICES, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    DL_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      dl_set_error("hipGetSymbolAddress returned NULL for the solver scratch");
+      return DL_EHIP;
+    }
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return DL_OK;
+}
+
+}  // namespace
+
+extern "C" dl_status dl_solve_noalloc(dl_problem* P, const dl_solve_opts* o, const double* lambda0,
+                                      double* lambda_out, dl_solve_stats* st) {
+  DL_CHECK_ARG(P && o && st && lambda_out, "NULL argument");
+  DL_TRY(check_schedule(o));
+  DL_CHECK_ARG(o->autotune_rounds == 0, "dl_solve_noalloc does not run the workgroup tuner (autotune_rounds must be 0)");
+  const int64_t mJ = (int64_t)P->m * P->J;
+  if (mJ > DL_NOALLOC_MAX_MJ) {
+    dl_set_error("dl_solve_noalloc: n_families * n_items exceeds its fixed state array (16384 rows)");
+    return DL_EUNSUPPORTED;
+  }
+  int dev = -1;
+  DL_HIP_TRY(hipGetDevice(&dev));
+  DL_CHECK_ARG(dev == P->device, "dl_solve_noalloc: make the problem's device current first");
+  unsigned char* base = nullptr;
+  DL_TRY(scratch_on_device(dev, &base));
+  auto t0 = std::chrono::steady_clock::now();
+  memset(st, 0, sizeof(*st));
+  // state of a solver without its own memory: nothing here is freed
+  dl_solver S;
+  S.P = P;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  S.lam = reinterpret_cast<double*>(take(sizeof(double) * mJ));
+  S.y = reinterpret_cast<double*>(take(sizeof(double) * mJ));
+  S.ax = reinterpret_cast<double*>(take(sizeof(double) * mJ));
+  S.mu_y = reinterpret_cast<float*>(take(sizeof(float) * mJ));
+  S.mu_lam = reinterpret_cast<float*>(take(sizeof(float) * mJ));
+  S.flag = reinterpret_cast<int*>(take(sizeof(int)));
+  if (off > DL_NOALLOC_BYTES) {
+    dl_set_error("internal: solver scratch layout exceeds its array");
+    return DL_EUNSUPPORTED;
+  }
+  // the previous call's contents stay in the array: clear the flag, set the start
+  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, P->stream, S.flag, 1, 0);
+  DL_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(init_state, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, lambda0, P->D, (int)mJ, P->J,
+                     P->eq_mask, S.lam, S.y, S.mu_y, S.mu_lam);
+  DL_HIP_TRY(hipGetLastError());
+  const dl_status rc = run_schedule(&S, o, lambda_out, st, t0);
+  // the state belongs to the array: make sure nothing of it is released
+  S.lam = S.y = S.ax = nullptr;
+  S.mu_y = S.mu_lam = nullptr;
+  S.flag = nullptr;
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
