@@ -403,6 +403,22 @@ dl_status dl_mlp_train_step(dl_mlp* mlp, const float* X, const float* target, in
 dl_status dl_solve_warm(dl_problem* prob, const dl_solve_opts* opts, int32_t n_cand, const double* const* cands,
                         double* lambda_out, dl_solve_stats* stats, int32_t* chosen, double* cand_dual);
 
+/* ----------------------------------------------------------------------- */
+/* Measurement                                                             */
+/* ----------------------------------------------------------------------- */
+/*
+ * Sustained read rate of the current device's HBM: a streaming kernel reads
+ * buf (device, bytes rounded down to 16-byte words, 16-byte aligned) reps
+ * times with 16-byte loads and nothing else, timed with HIP events on stream
+ * (a hipStream_t, NULL = default).  gbps (host) returns bytes read per second
+ * / 1e9.  sink (device, one word) receives an XOR of the data, so the loads
+ * cannot be elided.  This is the practical ceiling against which the gradient
+ * pass's bandwidth is reported (the pass is bound by HBM reads).  Synchronises
+ * the stream.  Not part of the paper's method.
+ */
+dl_status dl_read_bandwidth(const void* buf, int64_t bytes, int32_t reps, void* stream, unsigned* sink,
+                            double* gbps);
+
 /* Message for the last non-OK status on this thread. */
 const char* dl_last_error(void);
 

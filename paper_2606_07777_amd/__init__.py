@@ -156,6 +156,7 @@ SIGNATURES = {
     "dl_dual_grad": ([_VP, _VP, _D, _VP, _VP, _VP], _I32),
     "dl_project": ([_VP, _VP, _VP], _I32),
     "dl_solve": ([_VP, ctypes.POINTER(dl_solve_opts), _VP, _VP, ctypes.POINTER(dl_solve_stats)], _I32),
+    "dl_read_bandwidth": ([_VP, _I64, _I32, _VP, _VP, ctypes.POINTER(_D)], _I32),
     "dl_solve_noalloc": ([_VP, ctypes.POINTER(dl_solve_opts), _VP, _VP, ctypes.POINTER(dl_solve_stats)], _I32),
     "dl_solver_create": ([_VP, _VP, ctypes.POINTER(_VP)], _I32),
     "dl_solver_destroy": ([_VP], None),
@@ -501,6 +502,17 @@ class Batch:
         r = dl_tune_result()
         _check(load().dl_batch_get_tune(self.handle, ctypes.byref(r)))
         return {k: getattr(r, k) for k, _ in dl_tune_result._fields_}
+
+
+def read_bandwidth(nbytes: int, reps: int = 10, stream=None) -> float:
+    """dl_read_bandwidth on a fresh device buffer of nbytes: sustained HBM read GB/s."""
+    import torch
+    buf = torch.ones(max(nbytes // 4, 4), dtype=torch.float32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    g = ctypes.c_double()
+    _check(load().dl_read_bandwidth(_ptr(buf), buf.numel() * 4, int(reps), _stream(torch, stream), _ptr(sink),
+                                    ctypes.byref(g)))
+    return g.value
 
 
 class MLP:

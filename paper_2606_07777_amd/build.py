@@ -10,17 +10,22 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdualip.so")
-SOURCES = ["dl_problem.hip", "dl_grad.hip", "dl_solver.hip", "dl_batch.hip", "dl_mlp.hip"]
+SOURCES = ["dl_problem.hip", "dl_grad.hip", "dl_solver.hip", "dl_batch.hip", "dl_mlp.hip", "dl_measure.hip"]
 # The gradient-pass kernels are compiled once per variant (families class,
 # stored a, BF16 storage), each build its own object, so they compile in parallel.
 GRAD_VARIANTS = [(1, 0, 0), (1, 0, 1), (1, 1, 0), (1, 1, 1), (4, 1, 0), (4, 1, 1)]
+# The gradient pass never forms a NaN (its inputs are checked finite and its
+# padding lanes are kept at -inf / 0), so its float min / max need no NaN
+# quieting; the other sources keep IEEE NaN semantics (their divergence checks
+# test for NaN).
+GRAD_FLAGS = ["-fno-honor-nans"]
 
 
 def _units():
-    units = [(src, src.replace(".hip", ".o"), []) for src in SOURCES]
+    units = [(src, src.replace(".hip", ".o"), [], []) for src in SOURCES]
     for mf, a, bf in GRAD_VARIANTS:
         units.append(("dl_grad_variant.hip", f"dl_grad_v_{mf}_{a}_{bf}.o",
-                      [f"DL_GV_MF={mf}", f"DL_GV_A={a}", f"DL_GV_BF16={bf}"]))
+                      [f"DL_GV_MF={mf}", f"DL_GV_A={a}", f"DL_GV_BF16={bf}"], GRAD_FLAGS))
     return units
 
 
@@ -43,10 +48,10 @@ def build(verbose: bool = False, out: str = LIB, defines=(), objdir: str = None)
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
-    for src, oname, unit_defs in _units():
+    for src, oname, unit_defs, unit_flags in _units():
         obj = os.path.join(objdir, oname)
         objs.append(obj)
-        cmd = [hipcc, *HIPCC_FLAGS, *[f"-D{d}" for d in (*defines, *unit_defs)], "-I", INCLUDE, "-I", CSRC,
+        cmd = [hipcc, *HIPCC_FLAGS, *unit_flags, *[f"-D{d}" for d in (*defines, *unit_defs)], "-I", INCLUDE, "-I", CSRC,
                "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

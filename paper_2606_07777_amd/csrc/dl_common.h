@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,20 @@ constexpr int DL_KMAX_A = 8;
 // lanes may read up to 64*KMAX + 63 elements past a row start without
 // predication, and masks what lies past the row.
 constexpr int64_t DL_PAD = 4096;
+// Wide loads in the group path: each lane reads its row elements in aligned
+// chunks of four consecutive elements (one 16-byte load for FP32 / int32, one
+// 8-byte load for BF16) instead of one element per load.
+#ifndef DL_WIDE_LOADS
+#define DL_WIDE_LOADS 1
+#endif
+// Register slots per lane a row of degree d needs when served by 2^glog lanes.
+__host__ __device__ inline int64_t dl_slots(int64_t d, int glog) {
+  if (DL_WIDE_LOADS) return 4 * ((d + 3 + (4LL << glog) - 1) >> (glog + 2));
+  return (d + (1LL << glog) - 1) >> glog;
+}
+// Element stride between stored a families (a multiple of 64, so every
+// family's chunks stay as aligned as the c and idx arrays').
+__host__ __device__ inline int64_t dl_astride(int64_t nnz) { return ((nnz + 63) & ~(int64_t)63) + DL_PAD; }
 
 // A degree bucket: users [user_begin, user_end) of the reordered problem (sorted
 // by degree, longest first) served by groups of 2^glog lanes, 64/2^glog users
@@ -90,7 +105,7 @@ struct dl_grad_args {
   const void* aval;        // n_stored * nnz
   const int64_t* orig_rp;  // per reordered user: row start in the caller's order
   int64_t nnz;
-  int64_t astride;         // elements between stored a families (nnz + DL_PAD)
+  int64_t astride;         // elements between stored a families (dl_astride(nnz))
   int32_t J, m;
   int32_t a_slot[DL_MAX_FAMILIES];  // stored slot of family k, -1: a == 1
   float qscale[DL_MAX_FAMILIES];    // coarsest fixed-point scale of family k (max|a_k| * radius)

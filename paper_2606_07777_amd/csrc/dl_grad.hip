@@ -185,7 +185,7 @@ dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamm
   A.aval = P->aval;
   A.orig_rp = P->orig_rp;
   A.nnz = P->nnz;
-  A.astride = P->nnz + DL_PAD;
+  A.astride = dl_astride(P->nnz);
   A.J = P->J;
   A.m = P->m;
   for (int k = 0; k < DL_MAX_FAMILIES; ++k) {

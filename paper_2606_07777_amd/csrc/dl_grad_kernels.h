@@ -36,9 +36,12 @@
 //    workgroup and summed over workgroups by the update kernel.
 namespace {
 
+// Lane permutation within rows of 16 (every lane reads a valid source lane, so
+// bound_ctrl is immaterial; it lets the compiler fold the move into the DPP
+// form of the arithmetic instruction that consumes it).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float swz_xor16(float v) {
@@ -179,7 +182,46 @@ struct RowRegs {
   float a[HAS_A ? MF : 1][KMAX];
 };
 
-// Issues the loads of one task's rows (lane element e = lid + k*G, k < K).
+// Which row element a lane's register slot k holds.  With wide loads
+// (DL_WIDE_LOADS) the G lanes of a group read the row in chunks of four
+// consecutive elements starting at the row start rounded down to a multiple
+// of four: slot k of lane lid holds window element 4 (lid + (k/4) G) + k%4,
+// i.e. row element pos(k) = that - (s & 3); every chunk is one aligned 16-byte
+// (FP32) or 8-byte (BF16) load and the group's chunks of one step are
+// contiguous.  Otherwise slot k holds row element lid + k G (one element per
+// load).  Slots outside [0, d) are masked.
+template <int GLOG>
+__device__ __forceinline__ int slot_off(int k, int lid) {
+  constexpr int G = 1 << GLOG;
+  if constexpr (DL_WIDE_LOADS) return 4 * (lid + (k >> 2) * G) + (k & 3);
+  return lid + k * G;
+}
+// Row-start shift of the window (s mod 4 with wide loads, else 0).
+__device__ __forceinline__ int row_shift(const TaskMeta& m) {
+  if constexpr (DL_WIDE_LOADS) return (int)(m.s & 3);
+  return 0;
+}
+
+template <typename TV>
+__device__ __forceinline__ void ld4(const TV* p, float* out);
+template <>
+__device__ __forceinline__ void ld4<float>(const float* p, float* out) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  out[0] = v.x;
+  out[1] = v.y;
+  out[2] = v.z;
+  out[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void ld4<uint16_t>(const uint16_t* p, float* out) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);  // four BF16 values, little-endian pairs
+  out[0] = __uint_as_float(v.x << 16);
+  out[1] = __uint_as_float(v.x & 0xFFFF0000u);
+  out[2] = __uint_as_float(v.y << 16);
+  out[3] = __uint_as_float(v.y & 0xFFFF0000u);
+}
+
+// Issues the loads of one task's rows (slot k of lane lid: see slot_off).
 // Reads past a row end stay inside the padded arrays and are masked later.
 template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
@@ -187,9 +229,42 @@ __device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta&
   constexpr int G = 1 << GLOG;
   K = __builtin_amdgcn_readfirstlane(K);
   if constexpr ((MODE & M_VIN) != 0) {
+    // the caller's v has no alignment relation to the library's layout: one element per load
     const int d = (int)(m.e - m.s);
-    const float* vp = A.v_in + m.os + lid;
-    DL_FOR_K(k, KMAX, K) R.c[k] = (lid + k * G < d) ? vp[k * G] : 0.f;
+    const int sh = row_shift(m);
+    const float* vp = A.v_in + m.os;
+    DL_FOR_K(k, KMAX, K) {
+      const int p = slot_off<GLOG>(k, lid) - sh;
+      R.c[k] = (p >= 0 && p < d) ? vp[p] : 0.f;
+    }
+    return;
+  }
+  if constexpr (DL_WIDE_LOADS) {
+    const int64_t base = (m.s & ~(int64_t)3) + 4 * lid;
+    const int32_t* ip = A.idx + base;
+    const TV* cp = reinterpret_cast<const TV*>(A.cval) + base;
+#pragma unroll
+    for (int k4 = 0; k4 < KMAX / 4; ++k4) {
+      if (4 * k4 < K) {
+        const int4 v = *reinterpret_cast<const int4*>(ip + 4 * k4 * G);
+        R.j[4 * k4 + 0] = v.x;
+        R.j[4 * k4 + 1] = v.y;
+        R.j[4 * k4 + 2] = v.z;
+        R.j[4 * k4 + 3] = v.w;
+        ld4<TV>(cp + 4 * k4 * G, &R.c[4 * k4]);
+      }
+    }
+    if constexpr (HAS_A) {
+#pragma unroll
+      for (int f = 0; f < MF; ++f) {
+        if (f < A.m && A.a_slot[f] >= 0) {
+          const TV* ap = reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + base;
+#pragma unroll
+          for (int k4 = 0; k4 < KMAX / 4; ++k4)
+            if (4 * k4 < K) ld4<TV>(ap + 4 * k4 * G, &R.a[f][4 * k4]);
+        }
+      }
+    }
     return;
   }
   const int32_t* ip = A.idx + m.s + lid;
@@ -209,32 +284,44 @@ __device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta&
   }
 }
 
-// v = (c + sum_k a_k mu_k[j]) * (-1/gamma) in place of c; -inf past the row end.
+// v = (c + sum_k a_k mu_k[j]) * (-1/gamma) in place of c; -inf outside the row.
+// Slot k is inside the row when 0 <= slot_off(k, lid) - shift < d; with lo =
+// shift - 4 lid (wide) or -lid, that is the one unsigned compare
+// (c_k - lo) < d on the compile-time part c_k of the slot's offset.
 template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
                                          RowRegs<MF, HAS_A, KMAX>& R, const float* s_mu,
                                          float (&cc)[(MODE & M_REPAIR) ? KMAX : 1]) {
-  constexpr int G = 1 << GLOG;
   K = __builtin_amdgcn_readfirstlane(K);
-  const int d = (int)(m.e - m.s);
+  const unsigned d = (unsigned)(m.e - m.s);
+  const int lo = row_shift(m) - slot_off<GLOG>(0, lid);
+  const int mm = A.m;
   DL_FOR_KC(k, KMAX, K) {
     {
-      const bool in = lid + k * G < d;
+      const bool in = (unsigned)(slot_off<GLOG>(k, 0) - lo) < d;
       float val;
       if constexpr ((MODE & M_VIN) != 0) {
         val = R.c[k];
       } else {
         const int j = R.j[k];
-        float sdot = 0.f;
+        // the family loop has a uniform trip count: every read is issued
+        // unconditionally (rows of absent families read in-bounds LDS words
+        // that the select discards), so the reads of a chunk batch up
+        float sdot;
+        if constexpr (HAS_A) {
+          sdot = A.a_slot[0] >= 0 ? R.a[0][k] * s_mu[j] : s_mu[j];
+        } else {
+          sdot = s_mu[j];
+        }
 #pragma unroll
-        for (int f = 0; f < MF; ++f) {
-          if (f < A.m) {
-            float af = 1.f;
-            if constexpr (HAS_A) {
-              if (A.a_slot[f] >= 0) af = R.a[f][k];
-            }
-            sdot = fmaf(af, s_mu[f * A.J + j], sdot);
+        for (int f = 1; f < MF; ++f) {
+          const float muf = s_mu[(f < mm ? f : 0) * A.J + j];
+          float af = 1.f;
+          if constexpr (HAS_A) {
+            if (A.a_slot[f] >= 0) af = R.a[f][k];
           }
+          const float t = fmaf(af, muf, sdot);
+          sdot = f < mm ? t : sdot;
         }
         if constexpr ((MODE & M_REPAIR) != 0) cc[k] = R.c[k];
         val = (R.c[k] + sdot) * A.neg_inv_gamma;  // eq. 3 argument
@@ -333,7 +420,6 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
                                              unsigned long long* s_hist, double& acc,
                                              const float (&cc)[(MODE & M_REPAIR) ? KMAX : 1],
                                              const float (&qs)[DL_MAX_FAMILIES]) {
-  constexpr int G = 1 << GLOG;
   K = __builtin_amdgcn_readfirstlane(K);
   float (&v)[KMAX] = R.c;
   const float z = A.radius;
@@ -396,7 +482,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   auto emit = [&](int k, float x) {
     {
       if constexpr ((MODE & M_XOUT) != 0) {
-        if (lid + k * G < (int)(m.e - m.s)) A.x_out[m.os + lid + k * G] = x;
+        const int p = slot_off<GLOG>(k, lid) - row_shift(m);
+        if (p >= 0 && p < (int)(m.e - m.s)) A.x_out[m.os + p] = x;
       }
       if constexpr ((MODE & M_HIST) != 0) {
 #pragma unroll
@@ -414,7 +501,9 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
       if constexpr ((MODE & M_OBJ) != 0) {
         // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
         // (padding lanes hold v = -inf, whose term must not be formed)
-        const float term = x * fmaf(0.5f * A.gamma, x, -A.gamma * v[k]);
+        // (padding lanes hold v = -inf and x = 0: the clamp keeps their term an exact 0
+        // rather than 0 * inf, whatever the compiler does with the select)
+        const float term = x * fmaf(0.5f * A.gamma, x, -A.gamma * fmaxf(v[k], -0x1p100f));
         lobj += x > 0.f ? term : 0.f;
       }
       if constexpr ((MODE & M_REPAIR) != 0) {
@@ -452,8 +541,10 @@ __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucke
   const int lid = lane & (G - 1);
   constexpr bool need_os = (MODE & (M_VIN | M_XOUT)) != 0;
   auto kof = [&](const TaskMeta& m) {
-    // users are sorted longest first: lane 0 holds the task's longest row
+    // users are sorted longest first: lane 0 holds the task's longest row;
+    // slots per lane, whole chunks of four with wide loads (window shift <= 3)
     const int d0 = __builtin_amdgcn_readfirstlane((int)(m.e - m.s));
+    if constexpr (DL_WIDE_LOADS) return 4 * ((d0 + 3 + 4 * G - 1) >> (GLOG + 2));
     return (d0 + G - 1) >> GLOG;
   };
   float cc[(MODE & M_REPAIR) ? KMAX : 1];

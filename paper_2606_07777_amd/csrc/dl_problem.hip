@@ -68,7 +68,7 @@ __global__ void gather_rows(const int64_t* orig_rp, const int64_t* new_rp, int64
     else reinterpret_cast<float*>(c_out)[ns + e] = cv;
     for (int sl = 0; sl < n_stored; ++sl) {
       float av = a_in[(int64_t)fam_of_slot[sl] * nnz + os + e];
-      int64_t dst = (int64_t)sl * (nnz + DL_PAD) + ns + e;
+      int64_t dst = (int64_t)sl * dl_astride(nnz) + ns + e;
       if (bf16) reinterpret_cast<uint16_t*>(a_out)[dst] = dl_f32_to_bf16_rne(av);
       else reinterpret_cast<float*>(a_out)[dst] = av;
     }
@@ -96,10 +96,10 @@ __global__ void item_stats(const int32_t* idx, const void* aval, int64_t nnz, in
     const int32_t j = idx[e];
     atomicAdd(cnt + j, 1ull);
     for (int k = 0; k < m; ++k) {
-      double ak = slot[k] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[k] * (nnz + DL_PAD) + e) : 1.0;
+      double ak = slot[k] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[k] * dl_astride(nnz) + e) : 1.0;
       for (int l = k; l < m; ++l) {
         if (slot[k] < 0 && slot[l] < 0) continue;  // 1*1: equals cnt
-        double al = slot[l] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[l] * (nnz + DL_PAD) + e) : 1.0;
+        double al = slot[l] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[l] * dl_astride(nnz) + e) : 1.0;
         long long q = __double2ll_rn(ak * al * escale[k * m + l]);
         atomicAdd(M + ((int64_t)j * m + k) * m + l, (unsigned long long)q);
       }
@@ -268,10 +268,10 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   DL_CHECK_ARG(d->layout == DL_LAYOUT_BUCKETED || d->layout == DL_LAYOUT_WAVEFRONT, "unknown layout");
   const bool wavefront = d->layout == DL_LAYOUT_WAVEFRONT;
   auto code_of = [&](int64_t dg) -> int {
-    if (dg > 64 * (int64_t)kmax) return DL_LONG;
+    if (dl_slots(dg, 6) > kmax) return DL_LONG;
     if (wavefront) return 6;
     for (int gl = 0; gl <= 6; ++gl)
-      if (((dg + (1 << gl) - 1) >> gl) <= kmax) return gl;
+      if (dl_slots(dg, gl) <= kmax) return gl;
     return DL_LONG;
   };
   P->buckets.clear();
@@ -298,7 +298,7 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
       const int64_t upt = 64 >> code;
       for (int64_t x = u; x < ue; x += upt) {
         int64_t d0 = new_rp[x + 1] - new_rp[x];
-        int64_t K = (d0 + (1 << code) - 1) >> code;
+        int64_t K = dl_slots(d0, code);
         if (K > kmax) {
           dl_set_error("internal: bucket bound violated");
           return DL_EUNSUPPORTED;
@@ -323,13 +323,13 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   const bool bf16 = P->storage == DL_BF16;
   const size_t vb = bf16 ? 2 : 4;
   DL_TRY(dmalloc(P, &P->rp, (size_t)I + 1));
-  const int64_t stride = nnz + DL_PAD;
+  const int64_t stride = dl_astride(nnz);
   DL_TRY(dmalloc(P, &P->idx, (size_t)stride));
-  DL_HIP_TRY(hipMemsetAsync(P->idx + nnz, 0, sizeof(int32_t) * DL_PAD, st));
+  DL_HIP_TRY(hipMemsetAsync(P->idx + nnz, 0, sizeof(int32_t) * (size_t)(stride - nnz), st));
   {
     unsigned char* cv = nullptr;
     DL_TRY(dmalloc(P, &cv, (size_t)stride * vb));
-    DL_HIP_TRY(hipMemsetAsync(cv + (size_t)nnz * vb, 0, (size_t)DL_PAD * vb, st));
+    DL_HIP_TRY(hipMemsetAsync(cv + (size_t)nnz * vb, 0, (size_t)(stride - nnz) * vb, st));
     P->cval = cv;
   }
   if (P->n_stored > 0) {
@@ -540,7 +540,7 @@ dl_status dl_item_extremes(dl_problem* P, bool c_only) {
     const int kind = q == 0 ? 0 : (q == 1 ? 3 : (q % 2 == 0 ? 1 : 2));
     const int slot = q < 2 ? 0 : (q - 2) / 2;
     const void* val = q < 2 ? P->cval
-                             : (const void*)((const char*)P->aval + (size_t)slot * (size_t)(P->nnz + DL_PAD) *
+                             : (const void*)((const char*)P->aval + (size_t)slot * (size_t)dl_astride(P->nnz) *
                                                                        (bf16 ? 2 : 4));
     unsigned* out = P->ext + (size_t)q * J;
     if (bf16)
