@@ -100,7 +100,7 @@ enum : int {
 struct dl_grad_args {
   // reordered instance
   const int64_t* rp;       // I_new + 1
-  const int32_t* idx;      // nnz
+  const int32_t* idx;      // nnz item byte offsets 4 j (see dl_problem::idx)
   const void* cval;        // nnz, float or bf16
   const void* aval;        // n_stored * nnz
   const int64_t* orig_rp;  // per reordered user: row start in the caller's order
@@ -162,7 +162,7 @@ struct dl_problem {
 
   // reordered device layout
   int64_t* rp = nullptr;
-  int32_t* idx = nullptr;
+  int32_t* idx = nullptr;    // item of every element as the byte offset 4 j (J < 2^29)
   void* cval = nullptr;
   void* aval = nullptr;
   int64_t* orig_rp = nullptr;

@@ -121,16 +121,26 @@ __device__ __forceinline__ float ldv<uint16_t>(const uint16_t* p) {
   return __uint_as_float((uint32_t)(*p) << 16);
 }
 
-__device__ __forceinline__ void hist_add(unsigned long long* h, int r, float w, float qs) {
+// The library stores item indices as byte offsets jb = 4 j (the offset of item
+// j's word in an LDS array of 4-byte words), so an item's word is addressed
+// without a shift; its 8-byte histogram word sits at byte 2 jb.
+__device__ __forceinline__ float lds_word(const float* base, int byte_off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// Adds w = a x on the fixed-point grid 1/qs to the histogram word at byte
+// offset rb (round to nearest, ties to even).
+__device__ __forceinline__ void hist_add(unsigned long long* h, int rb, float w, float qs) {
   int q = __float2int_rn(w * qs);
-  if (q != 0) atomicAdd(h + r, (unsigned long long)(long long)q);
+  if (q != 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(h) + rb), (unsigned long long)(long long)q);
 }
 
 // w >= 0 (families with a == 1): rounds half up with one fused multiply-add and
 // a truncating convert; the 64-bit addend has a zero high word.
-__device__ __forceinline__ void hist_add_pos(unsigned long long* h, int r, float w, float qs) {
+__device__ __forceinline__ void hist_add_pos(unsigned long long* h, int rb, float w, float qs) {
   const uint32_t q = __float2uint_rz(fmaf(w, qs, 0.5f));
-  if (q != 0) atomicAdd(h + r, (unsigned long long)q);
+  if (q != 0) atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(h) + rb), (unsigned long long)q);
 }
 
 // ---------------------------------------------------------------------------
@@ -177,7 +187,7 @@ __device__ __forceinline__ TaskMeta load_meta(const dl_grad_args& A, const dl_bu
 
 template <int MF, bool HAS_A, int KMAX>
 struct RowRegs {
-  int j[KMAX];
+  int j[KMAX];     // item byte offsets (4 j)
   float c[KMAX];  // c, replaced in place by v
   float a[HAS_A ? MF : 1][KMAX];
 };
@@ -202,11 +212,24 @@ __device__ __forceinline__ int row_shift(const TaskMeta& m) {
   return 0;
 }
 
+// Wide loads of the row arrays.  (Plain loads: the nontemporal hint, which
+// speeds up a pure streaming read, made this pass 12% slower.)
+typedef int dl_v4i __attribute__((ext_vector_type(4)));
+typedef float dl_v4f __attribute__((ext_vector_type(4)));
+typedef unsigned dl_v2u __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void ld4_idx(const int32_t* p, int* out) {
+  const dl_v4i v = *reinterpret_cast<const dl_v4i*>(p);
+  out[0] = v.x;
+  out[1] = v.y;
+  out[2] = v.z;
+  out[3] = v.w;
+}
 template <typename TV>
 __device__ __forceinline__ void ld4(const TV* p, float* out);
 template <>
 __device__ __forceinline__ void ld4<float>(const float* p, float* out) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
+  const dl_v4f v = *reinterpret_cast<const dl_v4f*>(p);
   out[0] = v.x;
   out[1] = v.y;
   out[2] = v.z;
@@ -214,7 +237,8 @@ __device__ __forceinline__ void ld4<float>(const float* p, float* out) {
 }
 template <>
 __device__ __forceinline__ void ld4<uint16_t>(const uint16_t* p, float* out) {
-  const uint2 v = *reinterpret_cast<const uint2*>(p);  // four BF16 values, little-endian pairs
+  // four BF16 values, little-endian pairs
+  const dl_v2u v = *reinterpret_cast<const dl_v2u*>(p);
   out[0] = __uint_as_float(v.x << 16);
   out[1] = __uint_as_float(v.x & 0xFFFF0000u);
   out[2] = __uint_as_float(v.y << 16);
@@ -246,11 +270,7 @@ __device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta&
 #pragma unroll
     for (int k4 = 0; k4 < KMAX / 4; ++k4) {
       if (4 * k4 < K) {
-        const int4 v = *reinterpret_cast<const int4*>(ip + 4 * k4 * G);
-        R.j[4 * k4 + 0] = v.x;
-        R.j[4 * k4 + 1] = v.y;
-        R.j[4 * k4 + 2] = v.z;
-        R.j[4 * k4 + 3] = v.w;
+        ld4_idx(ip + 4 * k4 * G, &R.j[4 * k4]);
         ld4<TV>(cp + 4 * k4 * G, &R.c[4 * k4]);
       }
     }
@@ -303,19 +323,20 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
       if constexpr ((MODE & M_VIN) != 0) {
         val = R.c[k];
       } else {
-        const int j = R.j[k];
+        const int jb = R.j[k];
         // the family loop has a uniform trip count: every read is issued
         // unconditionally (rows of absent families read in-bounds LDS words
         // that the select discards), so the reads of a chunk batch up
         float sdot;
+        const float mu0 = lds_word(s_mu, jb);
         if constexpr (HAS_A) {
-          sdot = A.a_slot[0] >= 0 ? R.a[0][k] * s_mu[j] : s_mu[j];
+          sdot = A.a_slot[0] >= 0 ? R.a[0][k] * mu0 : mu0;
         } else {
-          sdot = s_mu[j];
+          sdot = mu0;
         }
 #pragma unroll
         for (int f = 1; f < MF; ++f) {
-          const float muf = s_mu[(f < mm ? f : 0) * A.J + j];
+          const float muf = lds_word(s_mu, (f < mm ? f : 0) * 4 * A.J + jb);
           float af = 1.f;
           if constexpr (HAS_A) {
             if (A.a_slot[f] >= 0) af = R.a[f][k];
@@ -430,18 +451,19 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
     theta = boxcut_theta<GLOG, KMAX, HAS_A>(v, K, z, A.upper);
   } else if (!box) {
     // pass A: largest two entries, positive part and its count
-    float m1 = -INFINITY, m2 = -INFINITY, sp = 0.f, cp = 0.f;
+    float m1 = -INFINITY, m2 = -INFINITY, sp = 0.f;
+    unsigned cpi = 0;  // integer count: one compare and one add-with-carry per element
     DL_FOR_KC(k, KMAX, K) {
       {
-        m2 = fmaxf(m2, fminf(m1, v[k]));
+        m2 = __builtin_amdgcn_fmed3f(m1, m2, v[k]);  // second largest of {m1 >= m2, v}
         m1 = fmaxf(m1, v[k]);
         sp += fmaxf(v[k], 0.f);
-        cp += v[k] > 0.f ? 1.f : 0.f;
+        cpi += v[k] > 0.f;
       }
     }
     gtop2<GLOG>(m1, m2);
     sp = gsum<GLOG>(sp);
-    cp = gsum<GLOG>(cp);
+    const float cp = gsum<GLOG>((float)cpi);
     const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
     bool done;
     if (m1 == -INFINITY || (!eq && sp <= z)) {
@@ -455,18 +477,19 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
       done = false;
     }
     for (int it = 0; it < 64 && __any(!done); ++it) {
-      float f = 0.f, cnt = 0.f, mina = INFINITY;
+      float f = 0.f, mina = INFINITY;
+      unsigned ci = 0;
       DL_FOR_KC(k, KMAX, K) {
         {
           const float t = v[k] - theta;
           f += fmaxf(t, 0.f);
           const bool act = t > 0.f;
-          cnt += act ? 1.f : 0.f;
+          ci += act;
           mina = fminf(mina, act ? v[k] : INFINITY);
         }
       }
       f = gsum<GLOG>(f);
-      cnt = gsum<GLOG>(cnt);
+      const float cnt = gsum<GLOG>((float)ci);
       mina = gmin<GLOG>(mina);
       if (!done) {
         // Newton step: the exact threshold of the active set {v > theta}; the
@@ -493,21 +516,20 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
             if constexpr (HAS_A) {
               if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
             }
-            if constexpr (HAS_A) hist_add(s_hist, f * A.J + R.j[k], w, qs[f]);
-            else hist_add_pos(s_hist, f * A.J + R.j[k], w, qs[f]);
+            if constexpr (HAS_A) hist_add(s_hist, f * 8 * A.J + 2 * R.j[k], w, qs[f]);
+            else hist_add_pos(s_hist, f * 8 * A.J + 2 * R.j[k], w, qs[f]);
           }
         }
       }
       if constexpr ((MODE & M_OBJ) != 0) {
         // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
-        // (padding lanes hold v = -inf, whose term must not be formed)
         // (padding lanes hold v = -inf and x = 0: the clamp keeps their term an exact 0
         // rather than 0 * inf, whatever the compiler does with the select)
         const float term = x * fmaf(0.5f * A.gamma, x, -A.gamma * fmaxf(v[k], -0x1p100f));
         lobj += x > 0.f ? term : 0.f;
       }
       if constexpr ((MODE & M_REPAIR) != 0) {
-        const float xt = s_rf[R.j[k]] * x;
+        const float xt = lds_word(s_rf, R.j[k]) * x;
         lobj += xt * fmaf(0.5f * A.gamma, xt, cc[k]);
       }
     }
@@ -598,7 +620,7 @@ __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucke
 // ---------------------------------------------------------------------------
 template <int MF, bool HAS_A, typename TV, int MODE>
 __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu, int64_t s, int64_t os, int e,
-                                        int& j, float& c, float (&af)[HAS_A ? MF : 1]) {
+                                        int& j /* item byte offset */, float& c, float (&af)[HAS_A ? MF : 1]) {
   if constexpr ((MODE & M_VIN) != 0) return A.v_in[os + e];
   j = A.idx[s + e];
   c = ldv<TV>(reinterpret_cast<const TV*>(A.cval) + s + e);
@@ -610,7 +632,7 @@ __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu
       if (HAS_A && A.a_slot[f] >= 0)
         a = ldv<TV>(reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + s + e);
       if (HAS_A) af[f] = a;
-      sdot = fmaf(a, s_mu[f * A.J + j], sdot);
+      sdot = fmaf(a, lds_word(s_mu, f * 4 * A.J + j), sdot);
     }
   }
   return (c + sdot) * A.neg_inv_gamma;
@@ -737,14 +759,14 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
       for (int f = 0; f < MF; ++f) {
         if (f < A.m) {
           float w = (HAS_A && A.a_slot[f] >= 0) ? af[HAS_A ? f : 0] * x : x;
-          if constexpr (HAS_A) hist_add(s_hist, f * A.J + j, w, qs[f]);
-          else hist_add_pos(s_hist, f * A.J + j, w, qs[f]);
+          if constexpr (HAS_A) hist_add(s_hist, f * 8 * A.J + 2 * j, w, qs[f]);
+          else hist_add_pos(s_hist, f * 8 * A.J + 2 * j, w, qs[f]);
         }
       }
     }
     if constexpr ((MODE & M_OBJ) != 0) lobj += x > 0.f ? x * fmaf(0.5f * A.gamma, x, -A.gamma * v) : 0.f;
     if constexpr ((MODE & M_REPAIR) != 0) {
-      const float xt = s_rf[j] * x;
+      const float xt = lds_word(s_rf, j) * x;
       lobj += xt * fmaf(0.5f * A.gamma, xt, c);
     }
   }

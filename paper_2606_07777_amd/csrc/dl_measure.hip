@@ -5,28 +5,27 @@
 
 namespace {
 
-// Grid-stride read of n16 16-byte words; each thread keeps four loads in
-// flight per step and folds them with XOR so none can be elided.  One word per
-// workgroup reaches memory (XOR-folded into *sink).
-__global__ void __launch_bounds__(256) stream_read(const uint4* __restrict__ src, int64_t n16,
+typedef unsigned dl_v4u __attribute__((ext_vector_type(4)));
+
+// Grid-stride read of n16 16-byte words with the nontemporal hint (the data is
+// streamed once); each thread keeps four loads in flight per step and folds
+// them with XOR so none can be elided.  One word per workgroup reaches memory
+// (XOR-folded into *sink).  Of the shapes measured (loads in flight per
+// thread, contiguous or strided blocks, 4 to 64 workgroups per compute unit,
+// with and without the hint), this one read fastest.
+__global__ void __launch_bounds__(256) stream_read(const dl_v4u* __restrict__ src, int64_t n16,
                                                    unsigned* __restrict__ sink) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+  dl_v4u acc = {0u, 0u, 0u, 0u};
   for (; i + 3 * stride < n16; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    acc.x ^= a.x ^ b.x ^ c.x ^ d.x;
-    acc.y ^= a.y ^ b.y ^ c.y ^ d.y;
-    acc.z ^= a.z ^ b.z ^ c.z ^ d.z;
-    acc.w ^= a.w ^ b.w ^ c.w ^ d.w;
+    const dl_v4u a = __builtin_nontemporal_load(src + i);
+    const dl_v4u b = __builtin_nontemporal_load(src + i + stride);
+    const dl_v4u c = __builtin_nontemporal_load(src + i + 2 * stride);
+    const dl_v4u d = __builtin_nontemporal_load(src + i + 3 * stride);
+    acc ^= a ^ b ^ c ^ d;
   }
-  for (; i < n16; i += stride) {
-    const uint4 a = src[i];
-    acc.x ^= a.x;
-    acc.y ^= a.y;
-    acc.z ^= a.z;
-    acc.w ^= a.w;
-  }
+  for (; i < n16; i += stride) acc ^= __builtin_nontemporal_load(src + i);
   unsigned v = acc.x ^ acc.y ^ acc.z ^ acc.w;
   for (int o = 32; o > 0; o >>= 1) v ^= __shfl_xor(v, o, 64);
   __shared__ unsigned sh[4];
@@ -46,9 +45,9 @@ extern "C" dl_status dl_read_bandwidth(const void* buf, int64_t bytes, int32_t r
   DL_HIP_TRY(hipGetDevice(&dev));
   DL_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t n16 = bytes / 16;
-  const unsigned grid = (unsigned)std::max(1, n_cu * 16);
+  const unsigned grid = (unsigned)std::max(1, n_cu * 64);
   // one untimed launch brings the kernel and the clocks up
-  hipLaunchKernelGGL(stream_read, dim3(grid), dim3(256), 0, st, (const uint4*)buf, n16, sink);
+  hipLaunchKernelGGL(stream_read, dim3(grid), dim3(256), 0, st, (const dl_v4u*)buf, n16, sink);
   DL_HIP_TRY(hipGetLastError());
   hipEvent_t e0, e1;
   DL_HIP_TRY(hipEventCreate(&e0));
@@ -60,7 +59,7 @@ extern "C" dl_status dl_read_bandwidth(const void* buf, int64_t bytes, int32_t r
   dl_status rc = DL_OK;
   if (hipEventRecord(e0, st) != hipSuccess) rc = DL_EHIP;
   for (int r = 0; r < reps && rc == DL_OK; ++r) {
-    hipLaunchKernelGGL(stream_read, dim3(grid), dim3(256), 0, st, (const uint4*)buf, n16, sink);
+    hipLaunchKernelGGL(stream_read, dim3(grid), dim3(256), 0, st, (const dl_v4u*)buf, n16, sink);
     if (hipGetLastError() != hipSuccess) rc = DL_EHIP;
   }
   float ms = 0.f;

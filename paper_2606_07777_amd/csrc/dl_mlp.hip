@@ -224,7 +224,7 @@ __global__ void feat_pass1(const int32_t* __restrict__ idx, const void* __restri
                            unsigned long long* __restrict__ cnt, unsigned* __restrict__ amax,
                            unsigned* __restrict__ mx, unsigned* __restrict__ mn) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = idx[e];
+    const int j = idx[e] >> 2;  // the problem stores item byte offsets (4 j)
     const float c = ldc<TV>(cval, e);
     atomicAdd(cnt + j, 1ull);
     atomicMax(amax, __float_as_uint(fabsf(c)));
@@ -238,7 +238,7 @@ template <typename TV>
 __global__ void feat_pass2(const int32_t* __restrict__ idx, const void* __restrict__ cval, int64_t nnz, double s1,
                            double s2, unsigned long long* __restrict__ q1, unsigned long long* __restrict__ q2) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = idx[e];
+    const int j = idx[e] >> 2;  // the problem stores item byte offsets (4 j)
     const double c = (double)ldc<TV>(cval, e);
     atomicAdd(q1 + j, (unsigned long long)__double2ll_rn(c * s1));
     atomicAdd(q2 + j, (unsigned long long)__double2ll_rn(c * c * s2));

@@ -62,7 +62,7 @@ __global__ void gather_rows(const int64_t* orig_rp, const int64_t* new_rp, int64
   int64_t os = orig_rp[u], ns = new_rp[u];
   int64_t d = new_rp[u + 1] - ns;
   for (int64_t e = lane; e < d; e += 64) {
-    idx_out[ns + e] = idx_in[os + e];
+    idx_out[ns + e] = 4 * idx_in[os + e];  // stored as the byte offset of the item's 4-byte word
     float cv = c_in[os + e];
     if (bf16) reinterpret_cast<uint16_t*>(c_out)[ns + e] = dl_f32_to_bf16_rne(cv);
     else reinterpret_cast<float*>(c_out)[ns + e] = cv;
@@ -93,7 +93,7 @@ __global__ void item_stats(const int32_t* idx, const void* aval, int64_t nnz, in
                            const int* slot, const double* escale, unsigned long long* cnt,
                            unsigned long long* M) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t j = idx[e];
+    const int32_t j = idx[e] >> 2;  // stored byte offsets
     atomicAdd(cnt + j, 1ull);
     for (int k = 0; k < m; ++k) {
       double ak = slot[k] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[k] * dl_astride(nnz) + e) : 1.0;
@@ -138,7 +138,7 @@ __global__ void item_extreme(const int32_t* __restrict__ idx, const TV* __restri
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     float v = ld<TV>(val, e);
     float q = kind == 0 ? fmaxf(0.f, -v) : (kind == 1 ? v : (kind == 2 ? -v : fabsf(v)));
-    atomicMax(&s_ext[idx[e]], dl_ord_enc(q));
+    atomicMax(&s_ext[idx[e] >> 2], dl_ord_enc(q));  // stored byte offsets
   }
   __syncthreads();
   for (int j = threadIdx.x; j < J; j += blockDim.x)
