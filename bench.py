@@ -68,15 +68,34 @@ def measured_traffic(args):
     return rec.get("traffic_bytes_per_pass")
 
 
-def cpu_baseline(inst, budget_s: float):
-    """The FP64 oracle on a bounded sample of the same instance: first S users."""
-    import numpy as np
+def host_cpu():
+    """Model name, logical CPUs and physical cores of this host (from /proc/cpuinfo)."""
+    model, cores = "unknown", set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model == "unknown":
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "physical_cores": len(cores) or None}
+
+
+def oracle_rate(sample, budget_s: float):
+    """(nnz*iter/s, iterations, seconds) of the FP64 oracle on sample within about budget_s."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    S = min(inst.n_users, 500_000)
-    sample = inst.user_slice(0, S)
-    # b scaled with the sample so the capacities keep binding
-    sample.b = inst.b * (S / inst.n_users)
     # marginal cost of an iteration: one call of 1 iteration and one of 3
     t = time.time()
     oracle.solve(sample, [1e-2], [1], jacobi=True, check_every=0)
@@ -88,10 +107,52 @@ def cpu_baseline(inst, budget_s: float):
     t = time.time()
     oracle.solve(sample, [1e-2], [iters], jacobi=True, check_every=0)
     el = time.time() - t
-    rate = sample.nnz * iters / el
-    return {"value": rate, "unit": "nnz*iter/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {S} users ({sample.nnz} nnz) of the same instance, b scaled by {S}/{inst.n_users}, "
-                      f"{iters} FP64 iterations in {el:.1f}s"}
+    return sample.nnz * iters / el, iters, el
+
+
+def cpu_rate_child(path: str, budget_s: float):
+    """Child process of cpu_baseline: the oracle on a saved sample with the
+    thread count its environment sets (prints one JSON line)."""
+    import numpy as np
+    import workloads
+    z = np.load(path)
+    sample = workloads.Instance("sample", int(z["n_users"]), int(z["n_items"]), 1, z["row_ptr"], z["item_idx"],
+                                z["c"], None, z["b"], "simplex_le", 1.0)
+    rate, iters, el = oracle_rate(sample, budget_s)
+    print(json.dumps({"rate": rate, "iters": iters, "seconds": el}), flush=True)
+
+
+def cpu_baseline(inst, budget_s: float):
+    """The FP64 oracle on a bounded sample of the same instance (its first S
+    users), with every host thread and, in a child process, with one thread."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    S = min(inst.n_users, 500_000)
+    sample = inst.user_slice(0, S)
+    # b scaled with the sample so the capacities keep binding
+    sample.b = inst.b * (S / inst.n_users)
+    rate, iters, el = oracle_rate(sample, budget_s)
+    out = {"value": rate, "unit": "nnz*iter/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {S} users ({sample.nnz} nnz) of the same instance, b scaled by {S}/{inst.n_users}, "
+                     f"{iters} FP64 iterations in {el:.1f}s", "host": host_cpu()}
+    # one thread: the same sample in a child process with OMP_NUM_THREADS=1
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "sample.npz")
+        np.savez(path, n_users=S, n_items=inst.n_items, row_ptr=sample.row_ptr, item_idx=sample.item_idx,
+                 c=sample.c, b=sample.b)
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-rate-child", path,
+                            "--cpu-budget", str(budget_s)], env=env, capture_output=True, text=True,
+                           timeout=max(120.0, 8 * budget_s))
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+            out["one_thread"] = {"value": one["rate"], "iters": one["iters"], "seconds": one["seconds"]}
+        else:
+            out["one_thread"] = {"error": r.stderr[-400:]}
+    return out
 
 
 def six_stage(prob, iters):
@@ -247,7 +308,8 @@ def member_rates(members, probs):
         t = s.timing()
         ms = t["grad_ms_total"] / t["n_grad"]
         rows.append({"users": m.n_users, "items": m.n_items, "nnz": m.nnz, "pass_ms": ms,
-                     "GBps": (8.0 * m.nnz + 8.0 * (m.n_users + 1)) / (ms * 1e-3) / 1e9})
+                     "bytes_per_pass": p.info()["bytes_per_pass"],
+                     "GBps": p.info()["bytes_per_pass"] / (ms * 1e-3) / 1e9})
         del s
     batch = dl.Batch(probs)
     _, _ = batch.solve(gammas=[1e-1], iters=[60], check_every=0, autotune=1)
@@ -260,7 +322,8 @@ def member_rates(members, probs):
     out = {"metric": "gradient-pass time of the uneven batch members, solo vs one batched pass", "unit": "ms",
            "solo_sum_ms": solo_ms, "batched_pass_ms": tr["pass_ms_model"],
            "solo_GBps_min": min(r["GBps"] for r in rows), "solo_GBps_max": max(r["GBps"] for r in rows),
-           "batched_GBps": 8.0 * nnz / (tr["pass_ms_model"] * 1e-3) / 1e9, "members": rows,
+           "batched_GBps": sum(r["bytes_per_pass"] for r in rows) / (tr["pass_ms_model"] * 1e-3) / 1e9,
+           "members": rows,
            "config": {"workload": f"uneven batch of {len(members)}"}}
     print(json.dumps(out), flush=True)
 
@@ -376,16 +439,19 @@ def main():
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="run a device copy of this size first (reference kernel for counter scaling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-rate-child", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--solve", action="store_true", help="also time a cold solve to a 1e-4 certified gap")
     ap.add_argument("--learned", default=os.path.join(ROOT, "paper_2606_07777_amd", "weights", "warmstart.npz"),
                     help="warm-start network for the time-to-gap comparison ('' = skip)")
     ap.add_argument("--eval-users", type=int, default=10_000_000)
     ap.add_argument("--eval-items", type=int, default=10_000)
-    ap.add_argument("--eval-chains", type=int, default=1)
-    ap.add_argument("--eval-days", type=int, default=3)
+    ap.add_argument("--eval-chains", type=int, default=4)
+    ap.add_argument("--eval-days", type=int, default=5)
     args = ap.parse_args()
 
+    if args.cpu_rate_child:
+        return cpu_rate_child(args.cpu_rate_child, args.cpu_budget)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
@@ -449,6 +515,10 @@ def main():
     cert = s.certificate()
     log(f"{args.steps} steps: {ms_step:.3f} ms/step, grad pass {grad_ms:.3f} ms ({achieved:.0f} GB/s), "
         f"update {upd_ms:.3f} ms; gap at gamma=1e-2 after warm-up: {cert['rel_gap']:.3e}")
+    # the practical read ceiling: a streaming read of as many bytes as one pass reads
+    ceiling = dl.read_bandwidth(int(bytes_pass), reps=20)
+    torch.cuda.empty_cache()
+    log(f"streaming read of {bytes_pass / 1e9:.2f} GB: {ceiling:.0f} GB/s (pass at {achieved / ceiling:.1%} of it)")
 
     out = {
         "metric": "nnz*iter/s of the dual-gradient pass plus fused update at 10M users x 10k items",
@@ -468,7 +538,10 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args),
-                     "kernel": "grad_pass", "kernel_ms": grad_ms, "bytes_per_pass": bytes_pass},
+                     "kernel": "grad_pass", "kernel_ms": grad_ms, "bytes_per_pass": bytes_pass,
+                     "ceiling": {"GBps": ceiling, "frac": achieved / ceiling,
+                                 "kernel": "dl_read_bandwidth: 16-byte nontemporal streaming reads of "
+                                           "bytes_per_pass bytes"}},
         "update_ms": upd_ms,
         "schedule": tune,
     }

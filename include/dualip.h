@@ -407,17 +407,16 @@ dl_status dl_solve_warm(dl_problem* prob, const dl_solve_opts* opts, int32_t n_c
 /* Measurement                                                             */
 /* ----------------------------------------------------------------------- */
 /*
- * Sustained read rate of the current device's HBM: a streaming kernel reads
- * buf (device, bytes rounded down to 16-byte words, 16-byte aligned) reps
- * times with 16-byte loads and nothing else, timed with HIP events on stream
- * (a hipStream_t, NULL = default).  gbps (host) returns bytes read per second
- * / 1e9.  sink (device, one word) receives an XOR of the data, so the loads
- * cannot be elided.  This is the practical ceiling against which the gradient
- * pass's bandwidth is reported (the pass is bound by HBM reads).  Synchronises
- * the stream.  Not part of the paper's method.
+ * Sustained read rate of the current device's HBM: the library allocates a
+ * buffer of bytes (rounded down to 16-byte words) with hipMalloc, and a
+ * streaming kernel reads it reps times with 16-byte loads and nothing else,
+ * timed with HIP events on stream (a hipStream_t, NULL = default).  gbps
+ * (host) returns bytes read per second / 1e9.  This is the practical ceiling
+ * against which the gradient pass's bandwidth is reported (the pass is bound
+ * by HBM reads).  DL_ENOMEM when the buffer does not fit.  Synchronises the
+ * stream and frees the buffer.  Not part of the paper's method.
  */
-dl_status dl_read_bandwidth(const void* buf, int64_t bytes, int32_t reps, void* stream, unsigned* sink,
-                            double* gbps);
+dl_status dl_read_bandwidth(int64_t bytes, int32_t reps, void* stream, double* gbps);
 
 /* Message for the last non-OK status on this thread. */
 const char* dl_last_error(void);

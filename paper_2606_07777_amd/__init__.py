@@ -156,7 +156,7 @@ SIGNATURES = {
     "dl_dual_grad": ([_VP, _VP, _D, _VP, _VP, _VP], _I32),
     "dl_project": ([_VP, _VP, _VP], _I32),
     "dl_solve": ([_VP, ctypes.POINTER(dl_solve_opts), _VP, _VP, ctypes.POINTER(dl_solve_stats)], _I32),
-    "dl_read_bandwidth": ([_VP, _I64, _I32, _VP, _VP, ctypes.POINTER(_D)], _I32),
+    "dl_read_bandwidth": ([_I64, _I32, _VP, ctypes.POINTER(_D)], _I32),
     "dl_solve_noalloc": ([_VP, ctypes.POINTER(dl_solve_opts), _VP, _VP, ctypes.POINTER(dl_solve_stats)], _I32),
     "dl_solver_create": ([_VP, _VP, ctypes.POINTER(_VP)], _I32),
     "dl_solver_destroy": ([_VP], None),
@@ -505,13 +505,10 @@ class Batch:
 
 
 def read_bandwidth(nbytes: int, reps: int = 10, stream=None) -> float:
-    """dl_read_bandwidth on a fresh device buffer of nbytes: sustained HBM read GB/s."""
+    """dl_read_bandwidth: sustained HBM read GB/s over a library-allocated buffer of nbytes."""
     import torch
-    buf = torch.ones(max(nbytes // 4, 4), dtype=torch.float32, device="cuda")
-    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
     g = ctypes.c_double()
-    _check(load().dl_read_bandwidth(_ptr(buf), buf.numel() * 4, int(reps), _stream(torch, stream), _ptr(sink),
-                                    ctypes.byref(g)))
+    _check(load().dl_read_bandwidth(int(nbytes), int(reps), _stream(torch, stream), ctypes.byref(g)))
     return g.value
 
 

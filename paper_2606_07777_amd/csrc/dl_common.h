@@ -47,6 +47,7 @@ constexpr int DL_MAX_BUCKETS = 8;
 constexpr int DL_LONG = 7;               // bucket code of rows longer than 64*KMAX
 constexpr int DL_MAX_MJ = 13000;         // m*J that fits the LDS accumulation (12 B per entry)
 constexpr int DL_MAX_FAMILIES = 4;
+static_assert(4 * DL_MAX_MJ <= 0xFFFF, "item byte offsets 4 j are stored in 16 bits");
 // Elements per lane in the group path: families with a == 1 only, and with a stored.
 #ifndef DL_KMAX_PLAIN
 #define DL_KMAX_PLAIN 12
@@ -62,16 +63,11 @@ constexpr int DL_KMAX_A = 8;
 // lanes may read up to 64*KMAX + 63 elements past a row start without
 // predication, and masks what lies past the row.
 constexpr int64_t DL_PAD = 4096;
-// Wide loads in the group path: each lane reads its row elements in aligned
-// chunks of four consecutive elements (one 16-byte load for FP32 / int32, one
-// 8-byte load for BF16) instead of one element per load.
-#ifndef DL_WIDE_LOADS
-#define DL_WIDE_LOADS 1
-#endif
-// Register slots per lane a row of degree d needs when served by 2^glog lanes.
+// Register slots per lane a row of degree d needs when served by 2^glog lanes
+// (chunks of four consecutive elements from the row start rounded down to a
+// multiple of four, so up to three leading slots belong to the previous row).
 __host__ __device__ inline int64_t dl_slots(int64_t d, int glog) {
-  if (DL_WIDE_LOADS) return 4 * ((d + 3 + (4LL << glog) - 1) >> (glog + 2));
-  return (d + (1LL << glog) - 1) >> glog;
+  return 4 * ((d + 3 + (4LL << glog) - 1) >> (glog + 2));
 }
 // Element stride between stored a families (a multiple of 64, so every
 // family's chunks stay as aligned as the c and idx arrays').
@@ -100,7 +96,7 @@ enum : int {
 struct dl_grad_args {
   // reordered instance
   const int64_t* rp;       // I_new + 1
-  const int32_t* idx;      // nnz item byte offsets 4 j (see dl_problem::idx)
+  const uint16_t* idx;     // nnz item byte offsets 4 j (see dl_problem::idx)
   const void* cval;        // nnz, float or bf16
   const void* aval;        // n_stored * nnz
   const int64_t* orig_rp;  // per reordered user: row start in the caller's order
@@ -162,7 +158,7 @@ struct dl_problem {
 
   // reordered device layout
   int64_t* rp = nullptr;
-  int32_t* idx = nullptr;    // item of every element as the byte offset 4 j (J < 2^29)
+  uint16_t* idx = nullptr;   // item of every element as the byte offset 4 j (J <= DL_MAX_MJ < 16384)
   void* cval = nullptr;
   void* aval = nullptr;
   int64_t* orig_rp = nullptr;

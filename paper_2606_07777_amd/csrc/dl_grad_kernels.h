@@ -187,30 +187,31 @@ __device__ __forceinline__ TaskMeta load_meta(const dl_grad_args& A, const dl_bu
 
 template <int MF, bool HAS_A, int KMAX>
 struct RowRegs {
-  int j[KMAX];     // item byte offsets (4 j)
-  float c[KMAX];  // c, replaced in place by v
+  uint32_t jp[KMAX / 2];  // item byte offsets (4 j, 16 bits each), slots 2i and 2i+1 packed
+  float c[KMAX];          // c, replaced in place by v
   float a[HAS_A ? MF : 1][KMAX];
 };
 
-// Which row element a lane's register slot k holds.  With wide loads
-// (DL_WIDE_LOADS) the G lanes of a group read the row in chunks of four
-// consecutive elements starting at the row start rounded down to a multiple
-// of four: slot k of lane lid holds window element 4 (lid + (k/4) G) + k%4,
-// i.e. row element pos(k) = that - (s & 3); every chunk is one aligned 16-byte
-// (FP32) or 8-byte (BF16) load and the group's chunks of one step are
-// contiguous.  Otherwise slot k holds row element lid + k G (one element per
-// load).  Slots outside [0, d) are masked.
+// Item byte offset held in slot k.
+template <int MF, bool HAS_A, int KMAX>
+__device__ __forceinline__ int item_off(const RowRegs<MF, HAS_A, KMAX>& R, int k) {
+  return (k & 1) ? (int)(R.jp[k >> 1] >> 16) : (int)(R.jp[k >> 1] & 0xFFFFu);
+}
+
+// Which row element a lane's register slot k holds.  The G lanes of a group
+// read the row in chunks of four consecutive elements starting at the row
+// start rounded down to a multiple of four: slot k of lane lid holds window
+// element 4 (lid + (k/4) G) + k%4, i.e. row element pos(k) = that - (s & 3).
+// Every chunk is one aligned load per array (8 bytes of item offsets, 16 bytes
+// of FP32 values or 8 of BF16) and the group's chunks of one step are
+// contiguous.  Slots outside [0, d) are masked.
 template <int GLOG>
 __device__ __forceinline__ int slot_off(int k, int lid) {
   constexpr int G = 1 << GLOG;
-  if constexpr (DL_WIDE_LOADS) return 4 * (lid + (k >> 2) * G) + (k & 3);
-  return lid + k * G;
+  return 4 * (lid + (k >> 2) * G) + (k & 3);
 }
-// Row-start shift of the window (s mod 4 with wide loads, else 0).
-__device__ __forceinline__ int row_shift(const TaskMeta& m) {
-  if constexpr (DL_WIDE_LOADS) return (int)(m.s & 3);
-  return 0;
-}
+// Row-start shift of the window (s mod 4).
+__device__ __forceinline__ int row_shift(const TaskMeta& m) { return (int)(m.s & 3); }
 
 // Wide loads of the row arrays.  (Plain loads: the nontemporal hint, which
 // speeds up a pure streaming read, made this pass 12% slower.)
@@ -218,12 +219,11 @@ typedef int dl_v4i __attribute__((ext_vector_type(4)));
 typedef float dl_v4f __attribute__((ext_vector_type(4)));
 typedef unsigned dl_v2u __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void ld4_idx(const int32_t* p, int* out) {
-  const dl_v4i v = *reinterpret_cast<const dl_v4i*>(p);
+// four 16-bit item offsets, kept packed in pairs
+__device__ __forceinline__ void ld4_idx(const uint16_t* p, uint32_t* out) {
+  const dl_v2u v = *reinterpret_cast<const dl_v2u*>(p);
   out[0] = v.x;
   out[1] = v.y;
-  out[2] = v.z;
-  out[3] = v.w;
 }
 template <typename TV>
 __device__ __forceinline__ void ld4(const TV* p, float* out);
@@ -263,42 +263,24 @@ __device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta&
     }
     return;
   }
-  if constexpr (DL_WIDE_LOADS) {
-    const int64_t base = (m.s & ~(int64_t)3) + 4 * lid;
-    const int32_t* ip = A.idx + base;
-    const TV* cp = reinterpret_cast<const TV*>(A.cval) + base;
+  const int64_t base = (m.s & ~(int64_t)3) + 4 * lid;
+  const uint16_t* ip = A.idx + base;
+  const TV* cp = reinterpret_cast<const TV*>(A.cval) + base;
 #pragma unroll
-    for (int k4 = 0; k4 < KMAX / 4; ++k4) {
-      if (4 * k4 < K) {
-        ld4_idx(ip + 4 * k4 * G, &R.j[4 * k4]);
-        ld4<TV>(cp + 4 * k4 * G, &R.c[4 * k4]);
-      }
+  for (int k4 = 0; k4 < KMAX / 4; ++k4) {
+    if (4 * k4 < K) {
+      ld4_idx(ip + 4 * k4 * G, &R.jp[2 * k4]);
+      ld4<TV>(cp + 4 * k4 * G, &R.c[4 * k4]);
     }
-    if constexpr (HAS_A) {
-#pragma unroll
-      for (int f = 0; f < MF; ++f) {
-        if (f < A.m && A.a_slot[f] >= 0) {
-          const TV* ap = reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + base;
-#pragma unroll
-          for (int k4 = 0; k4 < KMAX / 4; ++k4)
-            if (4 * k4 < K) ld4<TV>(ap + 4 * k4 * G, &R.a[f][4 * k4]);
-        }
-      }
-    }
-    return;
-  }
-  const int32_t* ip = A.idx + m.s + lid;
-  const TV* cp = reinterpret_cast<const TV*>(A.cval) + m.s + lid;
-  DL_FOR_K(k, KMAX, K) {
-    R.j[k] = ip[k * G];
-    R.c[k] = ldv<TV>(cp + k * G);
   }
   if constexpr (HAS_A) {
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
       if (f < A.m && A.a_slot[f] >= 0) {
-        const TV* ap = reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + m.s + lid;
-        DL_FOR_K(k, KMAX, K) R.a[f][k] = ldv<TV>(ap + k * G);
+        const TV* ap = reinterpret_cast<const TV*>(A.aval) + (int64_t)A.a_slot[f] * A.astride + base;
+#pragma unroll
+        for (int k4 = 0; k4 < KMAX / 4; ++k4)
+          if (4 * k4 < K) ld4<TV>(ap + 4 * k4 * G, &R.a[f][4 * k4]);
       }
     }
   }
@@ -323,7 +305,7 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
       if constexpr ((MODE & M_VIN) != 0) {
         val = R.c[k];
       } else {
-        const int jb = R.j[k];
+        const int jb = item_off(R, k);
         // the family loop has a uniform trip count: every read is issued
         // unconditionally (rows of absent families read in-bounds LDS words
         // that the select discards), so the reads of a chunk batch up
@@ -516,8 +498,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
             if constexpr (HAS_A) {
               if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
             }
-            if constexpr (HAS_A) hist_add(s_hist, f * 8 * A.J + 2 * R.j[k], w, qs[f]);
-            else hist_add_pos(s_hist, f * 8 * A.J + 2 * R.j[k], w, qs[f]);
+            if constexpr (HAS_A) hist_add(s_hist, f * 8 * A.J + 2 * item_off(R, k), w, qs[f]);
+            else hist_add_pos(s_hist, f * 8 * A.J + 2 * item_off(R, k), w, qs[f]);
           }
         }
       }
@@ -529,7 +511,7 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
         lobj += x > 0.f ? term : 0.f;
       }
       if constexpr ((MODE & M_REPAIR) != 0) {
-        const float xt = lds_word(s_rf, R.j[k]) * x;
+        const float xt = lds_word(s_rf, item_off(R, k)) * x;
         lobj += xt * fmaf(0.5f * A.gamma, xt, cc[k]);
       }
     }
@@ -566,8 +548,7 @@ __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucke
     // users are sorted longest first: lane 0 holds the task's longest row;
     // slots per lane, whole chunks of four with wide loads (window shift <= 3)
     const int d0 = __builtin_amdgcn_readfirstlane((int)(m.e - m.s));
-    if constexpr (DL_WIDE_LOADS) return 4 * ((d0 + 3 + 4 * G - 1) >> (GLOG + 2));
-    return (d0 + G - 1) >> GLOG;
+    return 4 * ((d0 + 3 + 4 * G - 1) >> (GLOG + 2));
   };
   float cc[(MODE & M_REPAIR) ? KMAX : 1];
   if constexpr (!PF) {

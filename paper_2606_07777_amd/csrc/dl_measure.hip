@@ -36,15 +36,23 @@ __global__ void __launch_bounds__(256) stream_read(const dl_v4u* __restrict__ sr
 
 }  // namespace
 
-extern "C" dl_status dl_read_bandwidth(const void* buf, int64_t bytes, int32_t reps, void* stream, unsigned* sink,
-                                       double* gbps) {
-  DL_CHECK_ARG(buf && sink && gbps && bytes >= 16 && reps >= 1, "bad argument");
-  DL_CHECK_ARG(((uintptr_t)buf & 15) == 0, "buf must be 16-byte aligned");
+extern "C" dl_status dl_read_bandwidth(int64_t bytes, int32_t reps, void* stream, double* gbps) {
+  DL_CHECK_ARG(gbps && bytes >= 16 && reps >= 1, "bad argument");
   hipStream_t st = (hipStream_t)stream;
   int dev = 0, n_cu = 0;
   DL_HIP_TRY(hipGetDevice(&dev));
   DL_HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t n16 = bytes / 16;
+  // a buffer of its own (hipMalloc), so the figure does not depend on how a
+  // caller's allocator laid its memory out; one extra word for the sink
+  unsigned char* buf = nullptr;
+  DL_HIP_TRY(hipMalloc((void**)&buf, (size_t)n16 * 16 + 256));
+  struct Free {
+    void* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{buf};
+  unsigned* sink = reinterpret_cast<unsigned*>(buf + (size_t)n16 * 16);
+  DL_HIP_TRY(hipMemsetAsync(buf, 1, (size_t)n16 * 16 + 256, st));
   const unsigned grid = (unsigned)std::max(1, n_cu * 64);
   // one untimed launch brings the kernel and the clocks up
   hipLaunchKernelGGL(stream_read, dim3(grid), dim3(256), 0, st, (const dl_v4u*)buf, n16, sink);
@@ -68,6 +76,7 @@ extern "C" dl_status dl_read_bandwidth(const void* buf, int64_t bytes, int32_t r
   if (rc == DL_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = DL_EHIP;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (rc == DL_OK && hipStreamSynchronize(st) != hipSuccess) rc = DL_EHIP;
   if (rc != DL_OK) {
     dl_set_error("timing the read kernel failed");
     return rc;

@@ -220,7 +220,7 @@ __device__ inline float ldc<uint16_t>(const void* p, int64_t e) {
 
 // Per item: count, max |c|, max c, min c (integer atomics: order-free).
 template <typename TV>
-__global__ void feat_pass1(const int32_t* __restrict__ idx, const void* __restrict__ cval, int64_t nnz,
+__global__ void feat_pass1(const uint16_t* __restrict__ idx, const void* __restrict__ cval, int64_t nnz,
                            unsigned long long* __restrict__ cnt, unsigned* __restrict__ amax,
                            unsigned* __restrict__ mx, unsigned* __restrict__ mn) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
@@ -235,7 +235,7 @@ __global__ void feat_pass1(const int32_t* __restrict__ idx, const void* __restri
 
 // Per item: sum c and sum c^2 on fixed-point grids (exact integer sums).
 template <typename TV>
-__global__ void feat_pass2(const int32_t* __restrict__ idx, const void* __restrict__ cval, int64_t nnz, double s1,
+__global__ void feat_pass2(const uint16_t* __restrict__ idx, const void* __restrict__ cval, int64_t nnz, double s1,
                            double s2, unsigned long long* __restrict__ q1, unsigned long long* __restrict__ q2) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     const int j = idx[e] >> 2;  // the problem stores item byte offsets (4 j)

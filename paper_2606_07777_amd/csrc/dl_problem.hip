@@ -55,14 +55,14 @@ __global__ void validate_rows(const int64_t* rp, const int32_t* idx, const float
 // One wavefront per reordered user: copy its row from the caller's CSR.
 __global__ void gather_rows(const int64_t* orig_rp, const int64_t* new_rp, int64_t I, const int32_t* idx_in,
                             const float* c_in, const float* a_in, int64_t nnz, int n_stored, const int* fam_of_slot,
-                            int bf16, int32_t* idx_out, void* c_out, void* a_out) {
+                            int bf16, uint16_t* idx_out, void* c_out, void* a_out) {
   int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (u >= I) return;
   int64_t os = orig_rp[u], ns = new_rp[u];
   int64_t d = new_rp[u + 1] - ns;
   for (int64_t e = lane; e < d; e += 64) {
-    idx_out[ns + e] = 4 * idx_in[os + e];  // stored as the byte offset of the item's 4-byte word
+    idx_out[ns + e] = (uint16_t)(4 * idx_in[os + e]);  // the byte offset of the item's 4-byte word
     float cv = c_in[os + e];
     if (bf16) reinterpret_cast<uint16_t*>(c_out)[ns + e] = dl_f32_to_bf16_rne(cv);
     else reinterpret_cast<float*>(c_out)[ns + e] = cv;
@@ -89,7 +89,7 @@ __device__ inline float ld<uint16_t>(const void* p, int64_t e) {
 }
 
 template <typename TV>
-__global__ void item_stats(const int32_t* idx, const void* aval, int64_t nnz, int32_t J, int32_t m,
+__global__ void item_stats(const uint16_t* idx, const void* aval, int64_t nnz, int32_t J, int32_t m,
                            const int* slot, const double* escale, unsigned long long* cnt,
                            unsigned long long* M) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
@@ -130,7 +130,7 @@ __global__ void regather_c(const int64_t* orig_rp, const int64_t* new_rp, int64_
 // in the order-preserving encoding: block-local LDS maxima, then one global
 // atomic maximum per item and block.
 template <typename TV>
-__global__ void item_extreme(const int32_t* __restrict__ idx, const TV* __restrict__ val, int64_t nnz, int J,
+__global__ void item_extreme(const uint16_t* __restrict__ idx, const TV* __restrict__ val, int64_t nnz, int J,
                              int kind, unsigned* __restrict__ out) {
   extern __shared__ unsigned s_ext[];
   for (int j = threadIdx.x; j < J; j += blockDim.x) s_ext[j] = DL_ORD_NEG_INF;
@@ -325,7 +325,7 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   DL_TRY(dmalloc(P, &P->rp, (size_t)I + 1));
   const int64_t stride = dl_astride(nnz);
   DL_TRY(dmalloc(P, &P->idx, (size_t)stride));
-  DL_HIP_TRY(hipMemsetAsync(P->idx + nnz, 0, sizeof(int32_t) * (size_t)(stride - nnz), st));
+  DL_HIP_TRY(hipMemsetAsync(P->idx + nnz, 0, sizeof(uint16_t) * (size_t)(stride - nnz), st));
   {
     unsigned char* cv = nullptr;
     DL_TRY(dmalloc(P, &cv, (size_t)stride * vb));
@@ -595,8 +595,8 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* P, dl_problem_info* o
   o->n_tasks = P->n_tasks;
   o->lhat = P->lhat;
   const double vb = P->storage == DL_BF16 ? 2.0 : 4.0;
-  // per nnz: item index + c + stored a's; per user: row pointer; per item: lam in, partial sums out
-  o->bytes_per_pass = (double)P->nnz * (4.0 + vb * (1 + P->n_stored)) + 8.0 * (double)(P->I + 1) +
+  // per nnz: 16-bit item offset + c + stored a's; per user: row pointer; per item: lam in
+  o->bytes_per_pass = (double)P->nnz * (2.0 + vb * (1 + P->n_stored)) + 8.0 * (double)(P->I + 1) +
                       (double)P->m * P->J * 4.0;
   o->device_bytes = P->device_bytes;
   o->max_degree = P->max_degree;
