@@ -47,6 +47,8 @@ class _Inst(ctypes.Structure):
         ("eq_mask", ctypes.c_int32),
         ("radius", ctypes.c_double),
         ("upper", ctypes.c_double),
+        ("global_count", ctypes.c_int32),
+        ("global_cap", ctypes.c_double),
     ]
 
 
@@ -135,11 +137,14 @@ class _Bound:
         self.c = np.ascontiguousarray(inst.c, dtype=np.float32)
         self.a = None if inst.a is None else np.ascontiguousarray(inst.a, dtype=np.float32)
         self.b = np.ascontiguousarray(inst.b, dtype=np.float64).reshape(-1)
+        cap = getattr(inst, "global_cap", None)
         self.s = _Inst(int(inst.n_users), int(inst.n_items), int(inst.n_families), self.rp.ctypes.data,
                        self.idx.ctypes.data, self.c.ctypes.data, _p(self.a), self.b.ctypes.data,
                        PROJ[inst.proj], int(getattr(inst, "eq_families", 0) or 0), float(inst.radius),
-                       float(getattr(inst, "upper", 0.0) or 0.0))
-        self.mJ = int(inst.n_families) * int(inst.n_items)
+                       float(getattr(inst, "upper", 0.0) or 0.0), int(cap is not None),
+                       float(cap) if cap is not None else 0.0)
+        # dual coordinates: m*J item rows, then the global-count row when present
+        self.mJ = int(inst.n_families) * int(inst.n_items) + (cap is not None)  # all dual rows
         self.nnz = int(self.rp[-1])
 
     @property

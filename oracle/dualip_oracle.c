@@ -58,7 +58,23 @@ typedef struct {
   int32_t eq_mask;         /* bit k: family k holds equality rows A_k x = b_k (free duals) */
   double radius;           /* z: simplex sum / box bound / box-cut sum */
   double upper;            /* u of the box-cut set {0 <= x <= u, sum x <= z} */
+  int32_t global_count;    /* 1: one more coupling row, sum over all (i,j) of x_ij <= global_cap */
+  double global_cap;       /* M of the global-count row */
 } orc_inst;
+
+/*
+ * Dual coordinates: the m*J item rows (family-major), then, with a global-count
+ * row (Section 5: one more coupling constraint sum_{(i,j) in E} x_ij <= M, i.e.
+ * one more row of A whose coefficients are all 1), one more coordinate at
+ * index m*J.
+ */
+static inline int64_t n_rows(const orc_inst* P) {
+  return (int64_t)P->n_families * P->n_items + (P->global_count ? 1 : 0);
+}
+static inline double row_b(const orc_inst* P, int64_t r) {
+  const int64_t mJ = (int64_t)P->n_families * P->n_items;
+  return r < mJ ? P->b[r] : P->global_cap;
+}
 
 #define ORC_CHUNKS 64
 
@@ -210,13 +226,14 @@ int orc_dual_grad_ex(const orc_inst* P, const double* lam, double gamma, double*
   if (!(gamma > 0.0)) return -1;
   const int64_t I = P->n_users;
   const int32_t J = P->n_items, m = P->n_families;
-  const int64_t mJ = (int64_t)m * J;
-  double* part = (double*)calloc((size_t)ORC_CHUNKS * (size_t)(mJ + 3), sizeof(double));
+  const int64_t mJ = (int64_t)m * J, nr = n_rows(P);
+  const double lam_g = P->global_count ? lam[mJ] : 0.0;  /* the global row's dual */
+  double* part = (double*)calloc((size_t)ORC_CHUNKS * (size_t)(nr + 3), sizeof(double));
   if (!part) return -2;
 
 #pragma omp parallel for schedule(dynamic, 1)
   for (int ch = 0; ch < ORC_CHUNKS; ++ch) {
-    double* acc = part + (size_t)ch * (size_t)(mJ + 3);
+    double* acc = part + (size_t)ch * (size_t)(nr + 3);
     int64_t u0 = I * ch / ORC_CHUNKS, u1 = I * (ch + 1) / ORC_CHUNKS;
     int64_t cap = 0;
     double *v = NULL, *x = NULL, *s = NULL;
@@ -232,6 +249,7 @@ int orc_dual_grad_ex(const orc_inst* P, const double* lam, double gamma, double*
         int32_t j = P->item_idx[r0 + e];
         double sum = 0.0;
         for (int k = 0; k < m; ++k) sum += coef(P, k, r0 + e) * lam[(int64_t)k * J + j];
+        sum += lam_g;                                       /* the global row's coefficient is 1 */
         s[e] = sum;                                         /* (A^T lam)_ij */
         v[e] = -((double)P->c[r0 + e] + sum) / gamma;       /* eq. 3 argument */
       }
@@ -240,27 +258,28 @@ int orc_dual_grad_ex(const orc_inst* P, const double* lam, double gamma, double*
         int32_t j = P->item_idx[r0 + e];
         double cij = (double)P->c[r0 + e];
         for (int k = 0; k < m; ++k) acc[(int64_t)k * J + j] += coef(P, k, r0 + e) * x[e];
-        acc[mJ] += cij * x[e];
-        acc[mJ + 1] += x[e] * x[e];
-        acc[mJ + 2] += s[e] * x[e];
+        if (P->global_count) acc[mJ] += x[e];
+        acc[nr] += cij * x[e];
+        acc[nr + 1] += x[e] * x[e];
+        acc[nr + 2] += s[e] * x[e];
         if (x_out) x_out[r0 + e] = x[e];
       }
     }
     free(v); free(x); free(s);
   }
-  double* ax = (double*)calloc((size_t)mJ, sizeof(double));
+  double* ax = (double*)calloc((size_t)nr, sizeof(double));
   double cx = 0.0, xx = 0.0, sx = 0.0;
   for (int ch = 0; ch < ORC_CHUNKS; ++ch) {
-    const double* acc = part + (size_t)ch * (size_t)(mJ + 3);
-    for (int64_t r = 0; r < mJ; ++r) ax[r] += acc[r];
-    cx += acc[mJ];
-    xx += acc[mJ + 1];
-    sx += acc[mJ + 2];
+    const double* acc = part + (size_t)ch * (size_t)(nr + 3);
+    for (int64_t r = 0; r < nr; ++r) ax[r] += acc[r];
+    cx += acc[nr];
+    xx += acc[nr + 1];
+    sx += acc[nr + 2];
   }
   double lb = 0.0;
-  for (int64_t r = 0; r < mJ; ++r) lb += lam[r] * P->b[r];
-  if (ax_out) memcpy(ax_out, ax, sizeof(double) * (size_t)mJ);
-  if (grad) for (int64_t r = 0; r < mJ; ++r) grad[r] = ax[r] - P->b[r];
+  for (int64_t r = 0; r < nr; ++r) lb += lam[r] * row_b(P, r);
+  if (ax_out) memcpy(ax_out, ax, sizeof(double) * (size_t)nr);
+  if (grad) for (int64_t r = 0; r < nr; ++r) grad[r] = ax[r] - row_b(P, r);
   /* eq. 2 at its minimiser: c^T x + (gamma/2)||x||^2 + lam^T A x - lam^T b */
   if (gval) *gval = cx + 0.5 * gamma * xx + sx - lb;
   if (cx_out) *cx_out = cx;
@@ -279,13 +298,16 @@ int orc_dual_grad(const orc_inst* P, const double* lam, double gamma, double* gr
 int orc_primal(const orc_inst* P, const double* x, double gamma, double* pobj, double* ax_out) {
   const int64_t nnz = P->row_ptr[P->n_users];
   const int32_t J = P->n_items, m = P->n_families;
+  const int64_t mJ = (int64_t)m * J;
   double cx = 0.0, xx = 0.0;
-  if (ax_out) memset(ax_out, 0, sizeof(double) * (size_t)m * (size_t)J);
+  if (ax_out) memset(ax_out, 0, sizeof(double) * (size_t)n_rows(P));
   for (int64_t e = 0; e < nnz; ++e) {
     cx += (double)P->c[e] * x[e];
     xx += x[e] * x[e];
-    if (ax_out)
+    if (ax_out) {
       for (int k = 0; k < m; ++k) ax_out[(int64_t)k * J + P->item_idx[e]] += coef(P, k, e) * x[e];
+      if (P->global_count) ax_out[mJ] += x[e];
+    }
   }
   if (pobj) *pobj = cx + 0.5 * gamma * xx;
   return 0;
@@ -327,6 +349,26 @@ int orc_scaling(const orc_inst* P, int jacobi, double* D, double* Lhat) {
         row += fabs(D[(int64_t)k * J + j] * M[((int64_t)j * m + k) * m + l] * D[(int64_t)l * J + j]);
       if (row > L) L = row;
     }
+  if (P->global_count) {
+    /* The global row g (all ones, scaled by D_g = 1/sqrt(nnz)) adds one row and
+     * column to A'A'^T: diagonal d_g = D_g^2 nnz and couplings c_kj = D_kj D_g
+     * sum_i a_kij.  Splitting A'A'^T into its block diagonal (the item blocks and
+     * d_g) plus the off-diagonal part [[0, c], [c^T, 0]], whose largest eigenvalue
+     * is ||c||_2, Weyl's inequality bounds lambda_max by max(L_items, d_g) + ||c||_2. */
+    const double Dg = (jacobi && nnz > 0) ? 1.0 / sqrt((double)nnz) : 1.0;
+    D[mJ] = Dg;
+    double* colsum = (double*)calloc((size_t)mJ, sizeof(double));
+    for (int64_t e = 0; e < nnz; ++e)
+      for (int k = 0; k < m; ++k) colsum[(int64_t)k * J + P->item_idx[e]] += coef(P, k, e);
+    double c2 = 0.0;
+    for (int64_t r = 0; r < mJ; ++r) {
+      const double c = D[r] * Dg * colsum[r];
+      c2 += c * c;
+    }
+    const double dg = Dg * Dg * (double)nnz;
+    L = (L > dg ? L : dg) + sqrt(c2);
+    free(colsum);
+  }
   *Lhat = L;
   free(M);
   return 0;
@@ -359,12 +401,21 @@ int orc_certificate(const orc_inst* P, const double* lam, double gamma, orc_stat
   const int32_t J = P->n_items, m = P->n_families;
   const int64_t mJ = (int64_t)m * J;
   double* x = (double*)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
-  double* ax = (double*)malloc(sizeof(double) * (size_t)mJ);
+  double* ax = (double*)malloc(sizeof(double) * (size_t)n_rows(P));
   double gval = 0.0, cx = 0.0, xx = 0.0;
   orc_dual_grad_ex(P, lam, gamma, ax, NULL, &gval, x, &cx, &xx);
   double* r = (double*)malloc(sizeof(double) * (size_t)J);
   double slack = 0.0, lg = 0.0;
-  for (int32_t j = 0; j < J; ++j) r[j] = 1.0;
+  /* global-count row: scaling every x by rho = min(1, M / sum x) makes it
+   * feasible and keeps every item row feasible (their factors only shrink) */
+  double rho = 1.0;
+  if (P->global_count) {
+    const double G = ax[mJ], M = P->global_cap, viol = G - M;
+    if (viol > slack) slack = viol;
+    lg -= lam[mJ] * viol;
+    if (G > M) rho = M > 0.0 ? M / G : 0.0;
+  }
+  for (int32_t j = 0; j < J; ++j) r[j] = rho;
   for (int k = 0; k < m; ++k)
     for (int32_t j = 0; j < J; ++j) {
       int64_t q = (int64_t)k * J + j;
@@ -415,8 +466,8 @@ typedef struct {
 
 int orc_solve(const orc_inst* P, const orc_solve_opts* o, const double* lam0, double* lam_out,
               orc_stats* st) {
-  const int32_t J = P->n_items, m = P->n_families;
-  const int64_t mJ = (int64_t)m * J;
+  const int32_t J = P->n_items;
+  const int64_t mJ = n_rows(P);  /* dual coordinates: item rows, then the global-count row */
   if (o->n_stages <= 0) return -1;
   double* D = (double*)malloc(sizeof(double) * (size_t)mJ);
   double Lhat = 0.0;

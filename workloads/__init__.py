@@ -156,6 +156,12 @@ class Instance:
     meta: dict = field(default_factory=dict)
     upper: float = 0.0   # u of the box-cut set {0 <= x <= u, sum x <= radius}
     eq_families: int = 0  # bit k: family k holds equality rows A_k x = b_k
+    global_cap: Optional[float] = None  # M of a global-count row sum_(i,j) x_ij <= M (None: no such row)
+
+    @property
+    def n_rows(self) -> int:
+        """Dual coordinates: m*J item rows, plus the global-count row when present."""
+        return self.n_families * self.n_items + (self.global_cap is not None)
 
     @property
     def nnz(self) -> int:
@@ -180,7 +186,7 @@ class Instance:
         a = None if self.a is None else np.ascontiguousarray(self.a[:, s:e])
         return Instance(self.name + f"[{first}:{first + count}]", count, self.n_items, self.n_families,
                         rp, self.item_idx[s:e].copy(), self.c[s:e].copy(), a, self.b.copy(),
-                        self.proj, self.radius, dict(self.meta), self.upper, self.eq_families)
+                        self.proj, self.radius, dict(self.meta), self.upper, self.eq_families, self.global_cap)
 
 
 def _generate(n_users, n_items, seed, deg_kind, deg_p1, deg_p2, deg_min, deg_max, item_kind,
