@@ -9,7 +9,9 @@
  *            box-cut {0 <= x_i <= u, sum x_i <= z} (Table 1's third kind)
  *   A        m coupling families; family k has one row per item j and
  *            A[(k,j),(i,j)] = a_kij (Definition 1: diagonal per-user blocks);
- *            a family may hold equality rows A_k x = b_k (free duals)
+ *            a family may hold equality rows A_k x = b_k (free duals); plus,
+ *            optionally, one global-count row sum_{(i,j)} x_ij <= M (the new
+ *            coupling constraint of Section 5: one more dual coordinate)
  * Dual (eq. 2): g(lam) = min_{x in C} c^T x + (gamma/2)||x||^2 + lam^T (A x - b)
  * Primal recovery (eq. 3): x*(lam) = Pi_C(-(A^T lam + c)/gamma)
  * Gradient (eq. 4): grad g(lam) = A x*(lam) - b
@@ -36,6 +38,9 @@
  *             the ABI.  Positive statuses are non-fatal.
  *   Units     lam, grad and A x are in the problem's own units even when
  *             Jacobi scaling is on (the scaling is internal to the solver).
+ *   Rows      Dual vectors (lam, grad, A x, solver states) have n_rows =
+ *             m*J + g entries: the m*J item rows family-major, then, with a
+ *             global-count row (g = 1), its coordinate last.
  *   Threads   A dl_problem or dl_solver must not be used from two threads at
  *             once; distinct objects are independent.
  */
@@ -103,6 +108,8 @@ typedef struct {
                                is NaN, max_slack is max |A x - b| on those rows (give the last stage a
                                fixed iteration count) */
   void* stream;             /* hipStream_t */
+  double global_cap;        /* M of the global-count row (global_count = 1), finite, >= 0 */
+  int32_t global_count;     /* 1: add the row sum over all (i,j) of x_ij <= global_cap (Section 5) */
 } dl_problem_desc;
 
 /* Facts about a created problem (all host values). */
@@ -120,6 +127,7 @@ typedef struct {
   int32_t bucket_glog[8];     /* log2 lanes per user of each degree bucket (7 = long rows) */
   int64_t bucket_users[8];
   float qscale[4];            /* fixed-point step of each family's accumulation is 1/qscale */
+  int64_t n_rows;             /* dual coordinates: m*J (+1 with the global-count row) */
 } dl_problem_info;
 
 /*
@@ -127,9 +135,10 @@ typedef struct {
  * builds the per-wavefront task table, computes the Jacobi scaling D and the
  * step bound lhat (Appendix C), and copies c and a into library storage.
  * Returns DL_EINVAL for malformed data (non-monotone row_ptr, item out of
- * range or repeated in a row, non-finite c/a/b, radius <= 0), DL_EUNSUPPORTED
- * when m*J exceeds the on-chip accumulation capacity (13,000), DL_ENOMEM or
- * DL_EHIP otherwise.  Synchronises the stream before returning.
+ * range or repeated in a row, non-finite c/a/b, radius <= 0, a negative or
+ * non-finite global_cap), DL_EUNSUPPORTED when m*J exceeds the on-chip
+ * accumulation capacity (13,000), DL_ENOMEM or DL_EHIP otherwise.
+ * Synchronises the stream before returning.
  */
 dl_status dl_problem_create(const dl_problem_desc* desc, dl_problem** out);
 
@@ -141,15 +150,15 @@ dl_status dl_problem_get_info(const dl_problem* prob, dl_problem_info* out);
 /*
  * New day on the same eligibility pattern (the recurring solves of Section 1):
  * replaces c (device, nnz, caller order; nullable = keep) and b (host, m*J;
- * nullable = keep).  a, the Jacobi scaling and the step bound are unchanged.
+ * nullable = keep; a global cap is kept).  a, the Jacobi scaling and the step bound are unchanged.
  * DL_EINVAL on non-finite input (c may then be partly replaced).  Synchronises.
  */
 dl_status dl_problem_update(dl_problem* prob, const float* c, const double* b);
 
 /*
  * ObjectiveFunction.calculate (Table 1; eqs. 2-4) at lam, gamma > 0.
- *   lambda    device, m*J: the dual point (used at FP32 in the per-nnz gather)
- *   grad      device, m*J, nullable: A x*(lam) - b
+ *   lambda    device, n_rows: the dual point (used at FP32 in the per-nnz gather)
+ *   grad      device, n_rows, nullable: A x*(lam) - b
  *   dual_obj  host, nullable: g(lam) in FP64 (synchronises)
  *   x         device, nnz, nullable: x*(lam) in the caller's CSR order
  */
@@ -194,8 +203,8 @@ typedef struct {
 } dl_solve_stats;
 
 /*
- * Runs the whole schedule from lambda0 (device, m*J, nullable = 0) and writes
- * the final lam (device, m*J) and stats (host).  The certificate (two extra
+ * Runs the whole schedule from lambda0 (device, n_rows, nullable = 0) and writes
+ * the final lam (device, n_rows) and stats (host).  The certificate (two extra
  * gradient passes) is evaluated every check_every iterations of the final
  * stage and at the end.  Returns DL_OK, DL_NOT_CONVERGED (cap reached, results
  * valid), DL_DIVERGED (non-finite iterate) or an error.
@@ -212,7 +221,7 @@ dl_status dl_solve(dl_problem* prob, const dl_solve_opts* opts, const double* la
  * the library (524,544 bytes per device, held until the process ends) instead of
  * memory allocated per call.  The problem's own buffers, made at create time,
  * are used as by dl_solve; the call itself calls no hipMalloc or hipFree.
- *   Limits  n_families * n_items <= 16384 (else DL_EUNSUPPORTED);
+ *   Limits  n_rows <= 16384 (else DL_EUNSUPPORTED);
  *           opts->autotune_rounds must be 0 (the tuner allocates; DL_EINVAL);
  *           the problem's device must be the current device (DL_EINVAL).
  *   Sharing every call on a device uses that device's one array and leaves
@@ -230,12 +239,12 @@ void dl_solver_destroy(dl_solver* s);
 dl_status dl_solver_set_stage(dl_solver* s, double gamma, double step_scale, int32_t reset);
 /* Enqueues n accelerated iterations (gradient pass + fused update each). No sync. */
 dl_status dl_solver_step(dl_solver* s, int64_t n);
-/* Current lam (device, m*J). */
+/* Current lam (device, n_rows). */
 dl_status dl_solver_get_lambda(dl_solver* s, double* lambda_out);
 
 /*
  * Checkpoint / resume of a stepwise solve.  dl_solver_export copies the dual
- * state into state (device, 2*m*J: the Jacobi-scaled lam' then the momentum
+ * state into state (device, 2*n_rows: the Jacobi-scaled lam' then the momentum
  * point y', in the solver's internal units: opaque) and fills meta (host).
  * dl_solver_import loads both into a solver of a problem with the same data
  * (same layout, scaling and step bound); the next dl_solver_step continues
@@ -247,7 +256,7 @@ typedef struct {
   double eta;         /* current step */
   double tk;          /* FISTA momentum sequence t_k (>= 1) */
   int64_t iters;      /* iterations taken */
-  int64_t m_times_j;  /* size check: m*J of the exporting problem */
+  int64_t m_times_j;  /* size check: n_rows of the exporting problem */
 } dl_solver_meta;
 dl_status dl_solver_export(dl_solver* s, double* state, dl_solver_meta* meta);
 dl_status dl_solver_import(dl_solver* s, const double* state, const dl_solver_meta* meta);
@@ -289,8 +298,8 @@ void dl_batch_destroy(dl_batch* batch); /* NULL-safe; does not destroy the probl
  * and the starting one (cost model, 4 per compute unit) is kept for the rest
  * of the solve (dl_batch_get_tune reports it).  The split never changes a
  * member's iterates: they stay bitwise equal to its solo solve.
- *   lambda0     host array of n device pointers (m_i*J_i each), or NULL (zeros)
- *   lambda_out  host array of n device pointers (m_i*J_i each)
+ *   lambda0     host array of n device pointers (n_rows of member i each), or NULL (zeros)
+ *   lambda_out  host array of n device pointers (n_rows of member i each)
  *   stats       host array of n records (iters and status per member)
  * Returns DL_OK when every member converged, DL_NOT_CONVERGED when some hit
  * the cap (results valid), or an error.
@@ -393,7 +402,7 @@ dl_status dl_mlp_train_step(dl_mlp* mlp, const float* X, const float* target, in
                             double* loss);
 
 /*
- * Judged warm start: each candidate start (device pointers, m*J each; a NULL
+ * Judged warm start: each candidate start (device pointers, n_rows each; a NULL
  * entry means lam = 0) is clamped to lam >= 0 and scored by the dual value
  * g_{gamma_0}(lam) at the schedule's first gamma; non-finite candidates score
  * -inf.  dl_solve then runs from the best.  chosen (nullable) returns its index,

@@ -52,6 +52,8 @@ class dl_problem_desc(ctypes.Structure):
         ("layout", ctypes.c_int32),
         ("eq_families", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("global_cap", ctypes.c_double),
+        ("global_count", ctypes.c_int32),
     ]
 
 
@@ -82,6 +84,7 @@ class dl_problem_info(ctypes.Structure):
         ("bucket_glog", ctypes.c_int32 * 8),
         ("bucket_users", ctypes.c_int64 * 8),
         ("qscale", ctypes.c_float * 4),
+        ("n_rows", ctypes.c_int64),
     ]
 
 
@@ -234,7 +237,7 @@ class Problem:
 
     def __init__(self, n_users, n_items, n_families, row_ptr, item_idx, c, a, b, proj="simplex_le",
                  radius=1.0, storage="f32", jacobi=True, wg_per_cu=0, stream=None, layout="bucketed", upper=0.0,
-                 eq_families=0):
+                 eq_families=0, global_cap=None):
         import torch
         self.torch = torch
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -256,20 +259,24 @@ class Problem:
         desc = dl_problem_desc(self.I, self.J, self.m, _ptr(self._rp), _ptr(self._idx), _ptr(self._c),
                                _ptr(self._a), bh.ctypes.data, PROJ[proj], STORAGE[storage], float(radius),
                                float(upper), int(jacobi), int(wg_per_cu), LAYOUT[layout], int(eq_families),
-                               self.stream)
+                               self.stream, float(global_cap) if global_cap is not None else 0.0,
+                               int(global_cap is not None))
         h = ctypes.c_void_p()
         _check(load().dl_problem_create(ctypes.byref(desc), ctypes.byref(h)))
         self.handle = h
         # the library copied what it needs
         self._rp = self._idx = self._c = self._a = None
-        self.nnz = self.info()["nnz"]
+        info = self.info()
+        self.nnz = info["nnz"]
+        self.nrow = info["n_rows"]  # dual coordinates: m*J, plus the global-count row
 
     @classmethod
     def from_instance(cls, inst, storage="f32", jacobi=True, wg_per_cu=0, stream=None, layout="bucketed"):
         """From any object with the attributes of a CSR matching instance."""
         return cls(inst.n_users, inst.n_items, inst.n_families, inst.row_ptr, inst.item_idx, inst.c, inst.a,
                    inst.b, inst.proj, inst.radius, storage, jacobi, wg_per_cu, stream, layout,
-                   float(getattr(inst, "upper", 0.0) or 0.0), int(getattr(inst, "eq_families", 0) or 0))
+                   float(getattr(inst, "upper", 0.0) or 0.0), int(getattr(inst, "eq_families", 0) or 0),
+                   getattr(inst, "global_cap", None))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -292,14 +299,20 @@ class Problem:
         d["qscale"] = list(o.qscale)[:self.m]
         return d
 
+    def _check_rows(self, t, what):
+        """Device dual vectors must hold n_rows entries (the library reads that many)."""
+        if t is not None and t.numel() != self.nrow:
+            raise ValueError(f"{what} has {t.numel()} entries, expected n_rows = {self.nrow}")
+
     def _empty(self, n, dt):
         return self.torch.empty(n, dtype=dt, device="cuda")
 
     def dual_grad(self, lam, gamma: float, want_obj=True, want_x=False):
-        """dl_dual_grad: (g(lam) or None, grad tensor [m*J] f64, x tensor [nnz] f32 or None)."""
+        """dl_dual_grad: (g(lam) or None, grad tensor [n_rows] f64, x tensor [nnz] f32 or None)."""
         torch = self.torch
         lam = lam.to(device="cuda", dtype=torch.float64).contiguous()
-        grad = self._empty(self.m * self.J, torch.float64)
+        self._check_rows(lam, "lam")
+        grad = self._empty(self.nrow, torch.float64)
         x = self._empty(self.nnz, torch.float32) if want_x else None
         g = ctypes.c_double()
         _check(load().dl_dual_grad(self.handle, _ptr(lam), float(gamma), _ptr(grad),
@@ -327,9 +340,10 @@ class Problem:
         o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
                           int(reset_momentum), int(autotune_rounds), float(step_scale))
         l0 = None if lam0 is None else lam0.to(device="cuda", dtype=torch.float64).contiguous()
+        self._check_rows(l0, "lam0")
         if out is None:
-            out = self._empty(self.m * self.J, torch.float64)
-        elif out.dtype != torch.float64 or out.numel() != self.m * self.J or not out.is_contiguous():
+            out = self._empty(self.nrow, torch.float64)
+        elif out.dtype != torch.float64 or out.numel() != self.nrow or not out.is_contiguous():
             raise ValueError("out must be a contiguous float64 tensor of m*J entries")
         st = dl_solve_stats()
         fn = load().dl_solve_noalloc if noalloc else load().dl_solve
@@ -363,10 +377,10 @@ class Problem:
                           int(reset_momentum), int(autotune_rounds), float(step_scale))
         ts = [None if c is None else c.to(device="cuda", dtype=torch.float64).contiguous() for c in candidates]
         for t in ts:
-            if t is not None and t.numel() != self.m * self.J:
-                raise ValueError(f"a candidate has {t.numel()} entries, expected {self.m * self.J}")
+            if t is not None and t.numel() != self.nrow:
+                raise ValueError(f"a candidate has {t.numel()} entries, expected {self.nrow}")
         arr = (ctypes.c_void_p * len(ts))(*[_ptr(t) for t in ts])
-        out = self._empty(self.m * self.J, torch.float64)
+        out = self._empty(self.nrow, torch.float64)
         st = dl_solve_stats()
         chosen = ctypes.c_int32(-1)
         duals = np.zeros(len(ts))
@@ -392,6 +406,7 @@ class Solver:
         self.prob = prob
         torch = prob.torch
         self._l0 = None if lam0 is None else lam0.to(device="cuda", dtype=torch.float64).contiguous()
+        prob._check_rows(self._l0, "lam0")
         h = ctypes.c_void_p()
         _check(load().dl_solver_create(prob.handle, _ptr(self._l0), ctypes.byref(h)))
         self.handle = h
@@ -414,14 +429,14 @@ class Solver:
         _check(load().dl_solver_step(self.handle, int(n)))
 
     def lam(self):
-        out = self.prob._empty(self.prob.m * self.prob.J, self.prob.torch.float64)
+        out = self.prob._empty(self.prob.nrow, self.prob.torch.float64)
         _check(load().dl_solver_get_lambda(self.handle, _ptr(out)))
         return out
 
     def export_state(self):
         """(state tensor on the device, meta dict): a checkpoint of the dual state."""
         torch = self.prob.torch
-        state = self.prob._empty(2 * self.prob.m * self.prob.J, torch.float64)
+        state = self.prob._empty(2 * self.prob.nrow, torch.float64)
         meta = dl_solver_meta()
         _check(load().dl_solver_export(self.handle, _ptr(state), ctypes.byref(meta)))
         return state, {f: getattr(meta, f) for f, _ in meta._fields_}
@@ -430,7 +445,7 @@ class Solver:
         """Loads a checkpoint from export_state (same problem data)."""
         torch = self.prob.torch
         state = state.to(device="cuda", dtype=torch.float64).contiguous()
-        if state.numel() != 2 * self.prob.m * self.prob.J:
+        if state.numel() != 2 * self.prob.nrow:
             raise ValueError("state size does not match the problem")
         m = dl_solver_meta(**meta)
         _check(load().dl_solver_import(self.handle, _ptr(state), ctypes.byref(m)))
@@ -486,11 +501,13 @@ class Batch:
         it = np.ascontiguousarray(iters, dtype=np.int64)
         o = dl_solve_opts(len(g), int(check_every), g.ctypes.data, it.ctypes.data, float(tol), int(max_iters),
                           int(reset_momentum), int(autotune), float(step_scale))
-        outs = [p._empty(p.m * p.J, torch.float64) for p in self.probs]
+        outs = [p._empty(p.nrow, torch.float64) for p in self.probs]
         out_arr = (ctypes.c_void_p * n)(*[_ptr(t) for t in outs])
         l0 = None
         if lam0 is not None:
             l0t = [t.to(device="cuda", dtype=torch.float64).contiguous() for t in lam0]
+            for p, t in zip(self.probs, l0t):
+                p._check_rows(t, "lam0")
             l0 = (ctypes.c_void_p * n)(*[_ptr(t) for t in l0t])
         stats = (dl_solve_stats * n)()
         _check(load().dl_batch_solve(self.handle, ctypes.byref(o), l0, out_arr, stats),

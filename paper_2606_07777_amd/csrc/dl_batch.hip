@@ -30,8 +30,8 @@ namespace {
 struct bupd {
   const unsigned long long* part;
   int n_slot;
-  int mJ, J;
-  int pad;
+  int mJ, J;        // item rows m*J, items J
+  int nrow;         // dual rows: m*J, then the global-count row when present
   const float* qs;  // the instance's fixed-point scales of the pass (device)
   int eq_mask;      // bit k: family k has free duals
   const double* D;
@@ -57,16 +57,17 @@ __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict_
   const bblk B = blk[blockIdx.x];
   const bupd& u = U[B.inst];
   const int r = B.r0 + (int)threadIdx.x;
-  if (r >= u.mJ) return;
+  if (r >= u.nrow) return;
   long long acc = 0;
-  for (int w = 0; w < u.n_slot; ++w) acc += (long long)u.part[(size_t)w * u.mJ + r];
-  const double ax = (double)acc / (double)u.qs[r / u.J];
+  for (int w = 0; w < u.n_slot; ++w) acc += (long long)u.part[(size_t)w * u.nrow + r];
+  const int k = r < u.mJ ? r / u.J : DL_MAX_FAMILIES;  // the global-count row has its own scale
+  const double ax = (double)acc / (double)u.qs[k];
   const double Dr = u.D[r];
   const double eta = step_scale * gamma / u.lhat;
   const double gs = Dr * (ax - u.b[r]);
   const double lo = u.lam[r];
   const double st = u.y[r] + eta * gs;
-  const double ln = ((u.eq_mask >> (r / u.J)) & 1) ? st : fmax(0.0, st);
+  const double ln = ((u.eq_mask >> k) & 1) ? st : fmax(0.0, st);
   const double yn = ln + beta * (ln - lo);
   u.lam[r] = ln;
   u.y[r] = yn;
@@ -174,7 +175,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
   for (size_t q = 0; q < live.size(); ++q) {
     const dl_problem* P = B->probs[live[q]];
     part_off[q] = part_need;
-    part_need += (size_t)std::max(1, w[q]) * (size_t)P->m * P->J;
+    part_need += (size_t)std::max(1, w[q]) * (size_t)P->nrow();
     lds = std::max(lds, dl_grad_lds_bytes(P, M_HIST));
   }
   if (part_need > B->part_cap) {
@@ -214,6 +215,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     u.part = A.part;
     u.n_slot = w[q];
     u.mJ = P->m * P->J;
+    u.nrow = (int)P->nrow();
     u.J = P->J;
     u.qs = P->qs_dev;
     u.eq_mask = P->eq_mask;
@@ -227,7 +229,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     u.lhat = P->lhat;
     const int ui = (int)B->h_upd.size();
     B->h_upd.push_back(u);
-    for (int r0 = 0; r0 < u.mJ; r0 += 256) B->h_blk.push_back({ui, r0});
+    for (int r0 = 0; r0 < u.nrow; r0 += 256) B->h_blk.push_back({ui, r0});
   }
   B->n_wg = (int)B->h_wgs.size();
   B->n_blk = (int)B->h_blk.size();
@@ -426,6 +428,9 @@ extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_bat
   *out = nullptr;
   DL_CHECK_ARG(n >= 1 && probs, "need at least one problem");
   for (int i = 0; i < n; ++i) DL_CHECK_ARG(probs[i], "NULL problem in batch");
+  // each member keeps per-pass state (fixed-point scales, partial slots) in its problem
+  for (int i = 0; i < n; ++i)
+    for (int k = i + 1; k < n; ++k) DL_CHECK_ARG(probs[i] != probs[k], "a problem appears twice in the batch");
   const dl_problem* P0 = probs[0];
   for (int i = 1; i < n; ++i) {
     const dl_problem* P = probs[i];

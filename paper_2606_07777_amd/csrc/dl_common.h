@@ -117,12 +117,12 @@ struct dl_grad_args {
   // iteration inputs
   float neg_inv_gamma;
   float gamma;
-  float pad0;
-  const float* mu;                  // m*J, lam in problem units (FP32)
+  int32_t glob;                     // 1: a global-count row (dual mu[m*J], count into part[.. + m*J])
+  const float* mu;                  // n_rows, lam in problem units (FP32)
   const float* rfac;                // J, repair factor (M_REPAIR)
   const float* v_in;                // nnz caller order (M_VIN)
   // outputs
-  unsigned long long* part;         // n_wg * m*J
+  unsigned long long* part;         // n_wg * n_rows (n_rows = m*J + glob)
   double* obj_part;                 // n_wg
   float* x_out;                     // nnz caller order, nullable
   unsigned long long* wg_clock;     // nullable: per slot (start, end) steady-clock ticks
@@ -144,6 +144,9 @@ struct dl_problem {
   double radius = 1.0;
   double upper = 0.0;    // u of the box-cut set
   int32_t eq_mask = 0;   // bit k: family k holds equality rows (free duals)
+  int32_t glob = 0;      // 1: one global-count row sum x <= gcap, dual coordinate m*J
+  double gcap = 0.0;
+  int64_t nrow() const { return (int64_t)m * J + glob; }
   int kmax = 16;
   int mf = 1;            // compiled family bound of the kernel variant (1 or 4)
   bool has_a = false;    // at least one stored family
@@ -154,7 +157,8 @@ struct dl_problem {
   // per-item extremes of the stored values (order-preserving uint encoding):
   // [max(0, -c) over the item's users], [max |c|], then per stored slot [max a], [max -a]
   unsigned* ext = nullptr;
-  float* qs_dev = nullptr;   // DL_MAX_FAMILIES fixed-point scales of the last histogram pass
+  float* qs_dev = nullptr;   // fixed-point scales of the last histogram pass: the families', then
+                             // the global-count row's at index DL_MAX_FAMILIES
 
   // reordered device layout
   int64_t* rp = nullptr;
@@ -175,19 +179,19 @@ struct dl_problem {
   bool clocking = false;
 
   // item space (device)
-  double* b = nullptr;       // m*J
-  double* D = nullptr;       // m*J Jacobi scaling (1 without Jacobi)
+  double* b = nullptr;       // n_rows (the global cap last)
+  double* D = nullptr;       // n_rows Jacobi scaling (1 without Jacobi)
   double lhat = 1.0;
   std::vector<double> b_host, D_host;
 
   // per-pass scratch (device)
-  unsigned long long* part = nullptr;  // n_wg * m*J
-  unsigned long long* acc = nullptr;   // m*J reduced sums, zero between passes
+  unsigned long long* part = nullptr;  // n_wg * n_rows
+  unsigned long long* acc = nullptr;   // n_rows reduced sums, zero between passes
   double* obj_part = nullptr;          // n_wg
   double* pobj_part = nullptr;         // n_wg
-  float* mu = nullptr;                 // m*J
+  float* mu = nullptr;                 // n_rows
   float* rfac = nullptr;               // J
-  double* lam_tmp = nullptr;           // m*J
+  double* lam_tmp = nullptr;           // n_rows
   double* cert_out = nullptr;          // 8 doubles
   int* upd_flag = nullptr;             // dl_problem_update's non-finite flag
   double* cert_host = nullptr;         // pinned, 8 doubles

@@ -67,13 +67,16 @@ __device__ void qscale_body(const dl_grad_args& A, float* out) {
   const float ig = -A.neg_inv_gamma;
   const float z = A.radius;
   const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
-  const float ulp = 0x1p-24f * (float)(m + 4);
+  const float ulp = 0x1p-24f * (float)(m + 5);
   float bk[DL_MAX_FAMILIES] = {0.f, 0.f, 0.f, 0.f};
+  float bg = 0.f;  // global-count row: bound on x itself
+  const float mug = A.glob ? A.mu[(size_t)m * J] : 0.f;
 #pragma unroll 4
   for (int j = threadIdx.x; j < J; j += blockDim.x) {
     const unsigned ec = A.ext[j];
     const float cneg = dl_ord_dec(ec), cabs = dl_ord_dec(A.ext[(size_t)J + j]);
-    float t = cneg, mag = cabs;
+    // the global-count dual shifts every v by -mu_g / gamma
+    float t = cneg - mug, mag = cabs + fabsf(mug);
     float aab[DL_MAX_FAMILIES];
 #pragma unroll
     for (int k = 0; k < DL_MAX_FAMILIES; ++k) {
@@ -95,6 +98,7 @@ __device__ void qscale_body(const dl_grad_args& A, float* out) {
 #pragma unroll
     for (int k = 0; k < DL_MAX_FAMILIES; ++k)
       if (k < m && any) bk[k] = fmaxf(bk[k], aab[k] * xm);
+    if (any) bg = fmaxf(bg, xm);
   }
 #pragma unroll
   for (int k = 0; k < DL_MAX_FAMILIES; ++k) {
@@ -110,6 +114,23 @@ __device__ void qscale_body(const dl_grad_args& A, float* out) {
       float qv = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
       qv = fminf(fmaxf(qv, A.qscale[k]), 0x1p60f);
       out[k] = qv;
+    }
+    __syncthreads();
+  }
+  if (A.glob) {
+    // |x| <= B_g per element: each addend below 2^31 on the grid 2^(30 - ceil log2 B_g),
+    // never coarser than for x <= radius; n_nonzeros * 2^31 < 2^63 bounds the sum
+    sh[threadIdx.x] = bg;
+    __syncthreads();
+    for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+      if ((int)threadIdx.x < s2) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s2]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const float B = sh[0] * (1.0f + 0x1p-16f);
+      const float coarse = ldexpf(1.f, 30 - (int)ceilf(log2f(fmaxf(z, 0x1p-30f))));
+      float qv = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
+      out[DL_MAX_FAMILIES] = fminf(fmaxf(qv, coarse), 0x1p60f);
     }
     __syncthreads();
   }
@@ -141,11 +162,12 @@ dl_status dl_launch_qscale_batch(const dl_grad_args* d_args, int n, hipStream_t 
 
 size_t dl_grad_lds_bytes(const dl_problem* P, int mode) {
   const size_t mJ = (size_t)P->m * P->J;
-  size_t mu_n = (mode & M_VIN) ? 0 : mJ;
+  size_t mu_n = (mode & M_VIN) ? 0 : (size_t)P->nrow();
   size_t rf_n = (mode & M_REPAIR) ? (size_t)P->J : 0;
   size_t off = ((mu_n + rf_n) * 4 + 15) & ~(size_t)15;
   size_t hist = (mode & M_HIST) ? mJ * 8 : 0;
-  return off + hist + DL_WAVES * sizeof(double);
+  // per-wavefront objective sums, then per-wavefront global counts
+  return off + hist + DL_WAVES * sizeof(double) + DL_WAVES * sizeof(unsigned long long);
 }
 
 dl_status dl_grad_prepare(const dl_problem* P) {
@@ -200,6 +222,7 @@ dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamm
   A.upper = (float)P->upper;
   A.neg_inv_gamma = (float)(-1.0 / gamma);
   A.gamma = (float)gamma;
+  A.glob = P->glob;
   A.mu = mu;
   A.qs_dev = P->qs_dev;
   A.ext = P->ext;

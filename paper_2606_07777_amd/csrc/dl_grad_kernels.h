@@ -143,6 +143,15 @@ __device__ __forceinline__ void hist_add_pos(unsigned long long* h, int rb, floa
   if (q != 0) atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(h) + rb), (unsigned long long)q);
 }
 
+// Per-lane accumulators of one pass: the FP64 objective terms, and the
+// fixed-point count of the global-count row (sum x on the grid 1/qs_g).
+struct LaneAcc {
+  double obj = 0.0;
+  unsigned long long gcnt = 0ull;
+};
+// Fixed-point scales of a pass: the families', then the global-count row's.
+constexpr int DL_NQS = DL_MAX_FAMILIES + 1;
+
 // ---------------------------------------------------------------------------
 // Group path: 2^GLOG lanes per user, up to KMAX elements per lane.
 // ---------------------------------------------------------------------------
@@ -298,6 +307,12 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
   const unsigned d = (unsigned)(m.e - m.s);
   const int lo = row_shift(m) - slot_off<GLOG>(0, lid);
   const int mm = A.m;
+  // the global-count row's dual: folded into the staged family-0 words when
+  // family 0 has a == 1, added here when its a is stored
+  float mug = 0.f;
+  if constexpr (HAS_A) {
+    if (A.glob && A.a_slot[0] >= 0) mug = lds_word(s_mu, 4 * mm * A.J);
+  }
   DL_FOR_KC(k, KMAX, K) {
     {
       const bool in = (unsigned)(slot_off<GLOG>(k, 0) - lo) < d;
@@ -312,7 +327,7 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
         float sdot;
         const float mu0 = lds_word(s_mu, jb);
         if constexpr (HAS_A) {
-          sdot = A.a_slot[0] >= 0 ? R.a[0][k] * mu0 : mu0;
+          sdot = A.a_slot[0] >= 0 ? fmaf(R.a[0][k], mu0, mug) : mu0;
         } else {
           sdot = mu0;
         }
@@ -420,9 +435,9 @@ __device__ __forceinline__ float boxcut_theta(const float (&v)[KMAX], int K, flo
 template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
                                              RowRegs<MF, HAS_A, KMAX>& R, const float* s_rf,
-                                             unsigned long long* s_hist, double& acc,
+                                             unsigned long long* s_hist, LaneAcc& acc,
                                              const float (&cc)[(MODE & M_REPAIR) ? KMAX : 1],
-                                             const float (&qs)[DL_MAX_FAMILIES]) {
+                                             const float (&qs)[DL_NQS]) {
   K = __builtin_amdgcn_readfirstlane(K);
   float (&v)[KMAX] = R.c;
   const float z = A.radius;
@@ -502,6 +517,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
             else hist_add_pos(s_hist, f * 8 * A.J + 2 * item_off(R, k), w, qs[f]);
           }
         }
+        // global-count row: x >= 0 on its own grid, summed per lane in 64 bits
+        if (A.glob) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
       }
       if constexpr ((MODE & M_OBJ) != 0) {
         // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
@@ -525,7 +542,7 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   } else {
     DL_FOR_KC(k, KMAX, K) emit(k, fmaxf(v[k] - theta, 0.f));
   }
-  if (MODE & (M_OBJ | M_REPAIR)) acc += (double)lobj;
+  if (MODE & (M_OBJ | M_REPAIR)) acc.obj += (double)lobj;
 }
 
 // The tasks t0, t0 + DL_WAVES, ... < t1 of one bucket.  With PF the next
@@ -534,8 +551,8 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
 template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucket& B, int64_t t0, int64_t t1,
                                            int lane, const float* s_mu, const float* s_rf,
-                                           unsigned long long* s_hist, double& acc,
-                                           const float (&qs)[DL_MAX_FAMILIES]) {
+                                           unsigned long long* s_hist, LaneAcc& acc,
+                                           const float (&qs)[DL_NQS]) {
   if (t0 >= t1) return;
   // keeps per-bucket lane arithmetic inside this bucket's code (otherwise it is
   // hoisted out of the kernel's bucket loop for every bucket at once and spills)
@@ -605,7 +622,8 @@ __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu
   if constexpr ((MODE & M_VIN) != 0) return A.v_in[os + e];
   j = A.idx[s + e];
   c = ldv<TV>(reinterpret_cast<const TV*>(A.cval) + s + e);
-  float sdot = 0.f;
+  // the global-count dual is folded into family 0's staged words when its a == 1
+  float sdot = (HAS_A && A.glob && A.a_slot[0] >= 0) ? lds_word(s_mu, 4 * A.m * A.J) : 0.f;
 #pragma unroll
   for (int f = 0; f < MF; ++f) {
     if (f < A.m) {
@@ -621,8 +639,8 @@ __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu
 
 template <int MF, bool HAS_A, typename TV, int MODE>
 __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, const dl_bucket& B, const float* s_mu,
-                                          const float* s_rf, unsigned long long* s_hist, int lane, double& acc,
-                                          const float (&qs)[DL_MAX_FAMILIES]) {
+                                          const float* s_rf, unsigned long long* s_hist, int lane, LaneAcc& acc,
+                                          const float (&qs)[DL_NQS]) {
   const int64_t u = B.user_begin + (t - B.task_begin);
   const int64_t s = A.rp[u];
   const int d = (int)(A.rp[u + 1] - s);
@@ -744,6 +762,7 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
           else hist_add_pos(s_hist, f * 8 * A.J + 2 * j, w, qs[f]);
         }
       }
+      if (A.glob) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
     }
     if constexpr ((MODE & M_OBJ) != 0) lobj += x > 0.f ? x * fmaf(0.5f * A.gamma, x, -A.gamma * v) : 0.f;
     if constexpr ((MODE & M_REPAIR) != 0) {
@@ -751,7 +770,7 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
       lobj += xt * fmaf(0.5f * A.gamma, xt, c);
     }
   }
-  if (MODE & (M_OBJ | M_REPAIR)) acc += (double)lobj;
+  if (MODE & (M_OBJ | M_REPAIR)) acc.obj += (double)lobj;
 }
 
 // One workgroup's share of a pass: tasks [w0, w1) of the instance A describes;
@@ -760,32 +779,41 @@ template <int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int64_t w1, int slot) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int mJ = A.m * A.J;
+  const int nrow = mJ + A.glob;
   const bool need_mu = !(MODE & M_VIN);
   float* s_mu = reinterpret_cast<float*>(smem);
-  const int mu_n = need_mu ? mJ : 0;
+  const int mu_n = need_mu ? nrow : 0;
   float* s_rf = s_mu + mu_n;
   const int rf_n = (MODE & M_REPAIR) ? A.J : 0;
   size_t off = ((size_t)(mu_n + rf_n) * 4 + 15) & ~(size_t)15;
   unsigned long long* s_hist = reinterpret_cast<unsigned long long*>(smem + off);
   const int hist_n = (MODE & M_HIST) ? mJ : 0;
   double* s_obj = reinterpret_cast<double*>(smem + off + (size_t)hist_n * 8);
+  unsigned long long* s_gc = reinterpret_cast<unsigned long long*>(s_obj + DL_WAVES);
 
   const int tid = threadIdx.x;
   unsigned long long t_start = 0;
   if (A.wg_clock && tid == 0) t_start = (unsigned long long)wall_clock64();
-  for (int r = tid; r < mu_n; r += DL_WG) s_mu[r] = A.mu[r];
+  if (need_mu) {
+    // family 0's words carry the global-count dual as well when its a == 1
+    const float mug0 = (A.glob && A.a_slot[0] < 0) ? A.mu[mJ] : 0.f;
+    for (int r = tid; r < mu_n; r += DL_WG) s_mu[r] = r < A.J ? A.mu[r] + mug0 : A.mu[r];
+  }
   for (int r = tid; r < rf_n; r += DL_WG) s_rf[r] = A.rfac[r];
   for (int r = tid; r < hist_n; r += DL_WG) s_hist[r] = 0ull;
   __syncthreads();
 
   const int wave = tid >> 6;
   const int lane = tid & 63;
-  double acc = 0.0;
-  // this pass's fixed-point scales (uniform)
-  float qs[DL_MAX_FAMILIES];
+  LaneAcc acc;
+  // this pass's fixed-point scales (uniform); the global-count row's last
+  float qs[DL_NQS];
 #pragma unroll
   for (int f = 0; f < DL_MAX_FAMILIES; ++f)
     qs[f] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(A.qs_dev ? A.qs_dev[f] : A.qscale[f])));
+  qs[DL_MAX_FAMILIES] = A.qs_dev ? __int_as_float(__builtin_amdgcn_readfirstlane(
+                                       __float_as_int(A.qs_dev[DL_MAX_FAMILIES])))
+                                 : 0x1p30f / fmaxf(A.radius, 0x1p-30f);
   for (int b = 0; b < A.n_buckets; ++b) {
     const dl_bucket& B = A.bk[b];
     const int64_t b1 = (b + 1 < A.n_buckets) ? A.bk[b + 1].task_begin : w1;
@@ -811,13 +839,25 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
   }
   if (MODE & (M_OBJ | M_REPAIR)) {
     // fixed-order FP64 reduction: lanes of a wavefront, then wavefronts in order
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) s_obj[wave] = acc;
+    double o_ = acc.obj;
+    for (int o = 32; o > 0; o >>= 1) o_ += __shfl_xor(o_, o, 64);
+    if (lane == 0) s_obj[wave] = o_;
+  }
+  if ((MODE & M_HIST) && A.glob) {
+    // integer sums: exact in any order
+    unsigned long long g_ = acc.gcnt;
+    for (int o = 32; o > 0; o >>= 1) g_ += __shfl_xor(g_, o, 64);
+    if (lane == 0) s_gc[wave] = g_;
   }
   __syncthreads();
   if (MODE & M_HIST) {
-    unsigned long long* dst = A.part + (size_t)slot * mJ;
+    unsigned long long* dst = A.part + (size_t)slot * nrow;
     for (int r = tid; r < mJ; r += DL_WG) dst[r] = s_hist[r];
+    if (A.glob && tid == 0) {
+      unsigned long long g_ = 0ull;
+      for (int w = 0; w < DL_WAVES; ++w) g_ += s_gc[w];
+      dst[mJ] = g_;
+    }
   }
   if ((MODE & (M_OBJ | M_REPAIR)) && tid == 0) {
     double tot = 0.0;

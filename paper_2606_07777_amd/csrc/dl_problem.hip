@@ -78,6 +78,7 @@ __global__ void gather_rows(const int64_t* orig_rp, const int64_t* new_rp, int64
 // Item statistics over the stored layout, as exact integer sums:
 //   cnt[j]                       number of users eligible for item j
 //   M[(j*m + k)*m + l], k <= l   sum_i a_kij a_lij, on a 2^-E_kl fixed-point grid
+//   S[j*m + k]                   sum_i a_kij (stored families), on a 2^-F_k grid
 // Values are those the kernels will read (after any BF16 rounding).
 template <typename TV>
 __device__ inline float ld(const void* p, int64_t e);
@@ -90,13 +91,14 @@ __device__ inline float ld<uint16_t>(const void* p, int64_t e) {
 
 template <typename TV>
 __global__ void item_stats(const uint16_t* idx, const void* aval, int64_t nnz, int32_t J, int32_t m,
-                           const int* slot, const double* escale, unsigned long long* cnt,
-                           unsigned long long* M) {
+                           const int* slot, const double* escale, const double* sscale, unsigned long long* cnt,
+                           unsigned long long* M, unsigned long long* S) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t j = idx[e] >> 2;  // stored byte offsets
     atomicAdd(cnt + j, 1ull);
     for (int k = 0; k < m; ++k) {
       double ak = slot[k] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[k] * dl_astride(nnz) + e) : 1.0;
+      if (slot[k] >= 0) atomicAdd(S + (int64_t)j * m + k, (unsigned long long)__double2ll_rn(ak * sscale[k]));
       for (int l = k; l < m; ++l) {
         if (slot[k] < 0 && slot[l] < 0) continue;  // 1*1: equals cnt
         double al = slot[l] >= 0 ? (double)ld<TV>(aval, (int64_t)slot[l] * dl_astride(nnz) + e) : 1.0;
@@ -181,6 +183,8 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   P->radius = d->radius;
   P->upper = d->upper;
   P->eq_mask = d->eq_families & ((1 << d->n_families) - 1);
+  P->glob = d->global_count ? 1 : 0;
+  P->gcap = P->glob ? d->global_cap : 0.0;
   P->jacobi = d->jacobi ? 1 : 0;
   P->stream = (hipStream_t)d->stream;
   DL_HIP_TRY(hipGetDevice(&P->device));
@@ -356,41 +360,46 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
 
   // ---- item statistics: counts and the m x m blocks of A A^T per item ----
   const int64_t mJ = (int64_t)m * J;
-  std::vector<double> esc((size_t)m * m, 0.0);
-  for (int k = 0; k < m; ++k)
+  const int64_t nrow = P->nrow();
+  std::vector<double> esc((size_t)m * m + m, 0.0);  // the M grids, then the S grids
+  for (int k = 0; k < m; ++k) {
     for (int l = k; l < m; ++l) {
       double bound = std::max<double>(1.0, (double)I) * (double)amax[k] * (double)amax[l];
       int E = 61 - (int)ceil(log2(std::max(bound, 1e-300)));
       esc[(size_t)k * m + l] = ldexp(1.0, E);
     }
-  unsigned long long *d_cnt = nullptr, *d_M = nullptr;
+    const double sb = std::max<double>(1.0, (double)I) * (double)amax[k];
+    esc[(size_t)m * m + k] = ldexp(1.0, 61 - (int)ceil(log2(std::max(sb, 1e-300))));
+  }
+  unsigned long long *d_cnt = nullptr, *d_M = nullptr, *d_S = nullptr;
   double* d_esc = nullptr;
   int* d_aslot = nullptr;
   DL_HIP_TRY(hipMalloc((void**)&d_cnt, sizeof(unsigned long long) * (size_t)J));
   FreeGuard g1{d_cnt};
-  DL_HIP_TRY(hipMalloc((void**)&d_M, sizeof(unsigned long long) * (size_t)J * m * m));
+  DL_HIP_TRY(hipMalloc((void**)&d_M, sizeof(unsigned long long) * (size_t)J * m * (m + 1)));
   FreeGuard g2{d_M};
-  DL_HIP_TRY(hipMalloc((void**)&d_esc, sizeof(double) * (size_t)m * m + sizeof(int) * DL_MAX_FAMILIES));
+  d_S = d_M + (size_t)J * m * m;
+  DL_HIP_TRY(hipMalloc((void**)&d_esc, sizeof(double) * esc.size() + sizeof(int) * DL_MAX_FAMILIES));
   FreeGuard g3{d_esc};
-  d_aslot = reinterpret_cast<int*>(d_esc + (size_t)m * m);
+  d_aslot = reinterpret_cast<int*>(d_esc + esc.size());
   DL_HIP_TRY(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * (size_t)J, st));
-  DL_HIP_TRY(hipMemsetAsync(d_M, 0, sizeof(unsigned long long) * (size_t)J * m * m, st));
-  DL_HIP_TRY(hipMemcpyAsync(d_esc, esc.data(), sizeof(double) * (size_t)m * m, hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipMemsetAsync(d_M, 0, sizeof(unsigned long long) * (size_t)J * m * (m + 1), st));
+  DL_HIP_TRY(hipMemcpyAsync(d_esc, esc.data(), sizeof(double) * esc.size(), hipMemcpyHostToDevice, st));
   DL_HIP_TRY(hipMemcpyAsync(d_aslot, P->a_slot, sizeof(int) * DL_MAX_FAMILIES, hipMemcpyHostToDevice, st));
   if (nnz > 0) {
     int blocks = (int)std::min<int64_t>((nnz + 255) / 256, (int64_t)n_cu * 64);
     if (bf16)
       hipLaunchKernelGGL(item_stats<uint16_t>, dim3(blocks), dim3(256), 0, st, P->idx, P->aval, nnz, J, m, d_aslot,
-                         d_esc, d_cnt, d_M);
+                         d_esc, d_esc + (size_t)m * m, d_cnt, d_M, d_S);
     else
       hipLaunchKernelGGL(item_stats<float>, dim3(blocks), dim3(256), 0, st, P->idx, P->aval, nnz, J, m, d_aslot,
-                         d_esc, d_cnt, d_M);
+                         d_esc, d_esc + (size_t)m * m, d_cnt, d_M, d_S);
     DL_HIP_TRY(hipGetLastError());
   }
-  std::vector<unsigned long long> cnt((size_t)J), Mq((size_t)J * m * m);
+  std::vector<unsigned long long> cnt((size_t)J), Mq((size_t)J * m * (m + 1));
   DL_HIP_TRY(hipMemcpyAsync(cnt.data(), d_cnt, sizeof(unsigned long long) * (size_t)J, hipMemcpyDeviceToHost, st));
-  DL_HIP_TRY(hipMemcpyAsync(Mq.data(), d_M, sizeof(unsigned long long) * (size_t)J * m * m, hipMemcpyDeviceToHost,
-                            st));
+  DL_HIP_TRY(hipMemcpyAsync(Mq.data(), d_M, sizeof(unsigned long long) * (size_t)J * m * (m + 1),
+                            hipMemcpyDeviceToHost, st));
   DL_HIP_TRY(hipStreamSynchronize(st));
 
   // M_j[k][l] in FP64, D = diag(1/||A_kj||_2) (1 on zero rows), lhat >= ||DA||^2
@@ -416,6 +425,26 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
         row += fabs(P->D_host[(size_t)k * J + j] * Mkl(j, k, l) * P->D_host[(size_t)l * J + j]);
       L = std::max(L, row);
     }
+  if (P->glob) {
+    // The global-count row g (coefficients 1, scaled by D_g = 1/sqrt(nnz)) adds
+    // the diagonal entry d_g = D_g^2 nnz and the couplings c_kj = D_kj D_g
+    // sum_i a_kij to A'A'^T; Weyl's inequality on the split into the block
+    // diagonal and [[0, c], [c^T, 0]] (largest eigenvalue ||c||_2) gives
+    // lambda_max <= max(L_items, d_g) + ||c||_2.
+    const double Dg = (P->jacobi && nnz > 0) ? 1.0 / sqrt((double)nnz) : 1.0;
+    double c2 = 0.0;
+    for (int32_t j = 0; j < J; ++j)
+      for (int k = 0; k < m; ++k) {
+        const double colsum = P->a_slot[k] < 0 ? (double)cnt[(size_t)j]
+                                               : (double)(long long)Mq[(size_t)J * m * m + (size_t)j * m + k] /
+                                                     esc[(size_t)m * m + k];
+        const double c = P->D_host[(size_t)k * J + j] * Dg * colsum;
+        c2 += c * c;
+      }
+    const double dg = Dg * Dg * (double)nnz;
+    L = std::max(L, dg) + sqrt(c2);
+    P->D_host.push_back(Dg);
+  }
   P->lhat = L > 0.0 ? L : 1.0;
 
   // fixed-point grid of each family's accumulation: |a x| <= amax * radius -> 2^30
@@ -427,23 +456,31 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
 
   // ---- item space and scratch ----
   P->b_host.assign(d->b, d->b + mJ);
-  DL_TRY(dmalloc(P, &P->b, (size_t)mJ));
-  DL_TRY(dmalloc(P, &P->D, (size_t)mJ));
-  DL_HIP_TRY(hipMemcpyAsync(P->b, P->b_host.data(), sizeof(double) * (size_t)mJ, hipMemcpyHostToDevice, st));
-  DL_HIP_TRY(hipMemcpyAsync(P->D, P->D_host.data(), sizeof(double) * (size_t)mJ, hipMemcpyHostToDevice, st));
-  DL_TRY(dmalloc(P, &P->part, (size_t)P->n_wg_cap * (size_t)mJ));
-  DL_TRY(dmalloc(P, &P->acc, (size_t)mJ));
-  DL_HIP_TRY(hipMemsetAsync(P->acc, 0, sizeof(unsigned long long) * (size_t)mJ, st));
+  if (P->glob) P->b_host.push_back(P->gcap);
+  DL_TRY(dmalloc(P, &P->b, (size_t)nrow));
+  DL_TRY(dmalloc(P, &P->D, (size_t)nrow));
+  DL_HIP_TRY(hipMemcpyAsync(P->b, P->b_host.data(), sizeof(double) * (size_t)nrow, hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipMemcpyAsync(P->D, P->D_host.data(), sizeof(double) * (size_t)nrow, hipMemcpyHostToDevice, st));
+  DL_TRY(dmalloc(P, &P->part, (size_t)P->n_wg_cap * (size_t)nrow));
+  DL_TRY(dmalloc(P, &P->acc, (size_t)nrow));
+  DL_HIP_TRY(hipMemsetAsync(P->acc, 0, sizeof(unsigned long long) * (size_t)nrow, st));
   DL_TRY(dmalloc(P, &P->obj_part, (size_t)P->n_wg_cap));
   DL_TRY(dmalloc(P, &P->pobj_part, (size_t)P->n_wg_cap));
-  DL_TRY(dmalloc(P, &P->mu, (size_t)mJ));
+  DL_TRY(dmalloc(P, &P->mu, (size_t)nrow));
   DL_TRY(dmalloc(P, &P->rfac, (size_t)J));
-  DL_TRY(dmalloc(P, &P->lam_tmp, (size_t)mJ));
+  DL_TRY(dmalloc(P, &P->lam_tmp, (size_t)nrow));
   DL_TRY(dmalloc(P, &P->cert_out, 16));
   DL_HIP_TRY(hipHostMalloc((void**)&P->cert_host, sizeof(double) * 16, hipHostMallocDefault));
-  DL_TRY(dmalloc(P, &P->qs_dev, (size_t)DL_MAX_FAMILIES));
+  DL_TRY(dmalloc(P, &P->qs_dev, (size_t)DL_MAX_FAMILIES + 4));
   DL_TRY(dmalloc(P, &P->upd_flag, 1));
-  DL_HIP_TRY(hipMemcpyAsync(P->qs_dev, P->qscale, sizeof(float) * DL_MAX_FAMILIES, hipMemcpyHostToDevice, st));
+  {
+    // the families' coarsest scales, then the global-count row's (x <= radius per element)
+    float q0[DL_MAX_FAMILIES + 4] = {0};
+    for (int k = 0; k < DL_MAX_FAMILIES; ++k) q0[k] = P->qscale[k];
+    q0[DL_MAX_FAMILIES] = (float)ldexp(1.0, 30 - (int)ceil(log2(std::max(d->radius, 1e-30))));
+    DL_HIP_TRY(hipMemcpyAsync(P->qs_dev, q0, sizeof(q0), hipMemcpyHostToDevice, st));
+    DL_HIP_TRY(hipStreamSynchronize(st));
+  }
   DL_TRY(dmalloc(P, &P->ext, (size_t)J * (size_t)(2 + 2 * P->n_stored)));
   DL_TRY(dl_item_extremes(P, false));
   DL_TRY(dl_grad_prepare(P));
@@ -506,6 +543,9 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** ou
   DL_CHECK_ARG(d->radius > 0.0 && isfinite(d->radius), "radius must be positive and finite");
   const int64_t mJ = (int64_t)d->n_items * d->n_families;
   for (int64_t r = 0; r < mJ; ++r) DL_CHECK_ARG(isfinite(d->b[r]), "b has a non-finite entry");
+  DL_CHECK_ARG(d->global_count == 0 || d->global_count == 1, "global_count must be 0 or 1");
+  DL_CHECK_ARG(!d->global_count || (isfinite(d->global_cap) && d->global_cap >= 0.0),
+               "global_cap must be finite and >= 0");
   if (mJ > DL_MAX_MJ) {
     dl_set_error("n_families * n_items exceeds the on-chip accumulation capacity (13000)");
     return DL_EUNSUPPORTED;
@@ -577,6 +617,7 @@ extern "C" dl_status dl_problem_update(dl_problem* P, const float* c, const doub
   }
   if (b) {
     P->b_host.assign(b, b + mJ);
+    if (P->glob) P->b_host.push_back(P->gcap);  // the global cap is kept
     DL_HIP_TRY(hipMemcpyAsync(P->b, P->b_host.data(), sizeof(double) * mJ, hipMemcpyHostToDevice, st));
     DL_HIP_TRY(hipStreamSynchronize(st));
   }
@@ -597,7 +638,8 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* P, dl_problem_info* o
   const double vb = P->storage == DL_BF16 ? 2.0 : 4.0;
   // per nnz: 16-bit item offset + c + stored a's; per user: row pointer; per item: lam in
   o->bytes_per_pass = (double)P->nnz * (2.0 + vb * (1 + P->n_stored)) + 8.0 * (double)(P->I + 1) +
-                      (double)P->m * P->J * 4.0;
+                      (double)P->nrow() * 4.0;
+  o->n_rows = P->nrow();
   o->device_bytes = P->device_bytes;
   o->max_degree = P->max_degree;
   o->n_buckets = (int32_t)P->buckets.size();

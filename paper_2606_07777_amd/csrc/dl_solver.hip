@@ -18,7 +18,8 @@ namespace {
 struct upd_args {
   unsigned long long* acc;  // reduced per-item sums (read and cleared)
   int n_wg;
-  int mJ, J;
+  int mJ, J;        // item rows m*J, items J
+  int nrow;         // dual rows: m*J, then the global-count row when present
   const float* qs;  // fixed-point scale of each family in the pass being reduced (device)
   int eq_mask;      // bit k: family k has free duals (equality rows)
   const double* D;
@@ -61,8 +62,8 @@ __device__ __forceinline__ double take_sum(unsigned long long* acc, int r) {
 // and publish the next gather point D y'_+ (FP32).
 __global__ void update_kernel(upd_args U) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= U.mJ) return;
-  const int k = r / U.J;
+  if (r >= U.nrow) return;
+  const int k = r < U.mJ ? r / U.J : DL_MAX_FAMILIES;  // the global-count row has its own scale
   const double ax = take_sum(U.acc, r) / (double)U.qs[k];
   const double Dr = U.D[r];
   const double gs = Dr * (ax - U.b[r]);
@@ -80,8 +81,8 @@ __global__ void update_kernel(upd_args U) {
 // A x (and A x - b) from the partials, no step.
 __global__ void reduce_kernel(upd_args U) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= U.mJ) return;
-  const int k = r / U.J;
+  if (r >= U.nrow) return;
+  const int k = r < U.mJ ? r / U.J : DL_MAX_FAMILIES;
   const double ax = take_sum(U.acc, r) / (double)U.qs[k];
   if (U.ax_out) U.ax_out[r] = ax;
   if (U.grad_out) U.grad_out[r] = ax - U.b[r];
@@ -147,17 +148,28 @@ __device__ double block_max(double v, double* sh) {
 }
 
 // Certificate, item part (one workgroup): repair factor r_j =
-// min_k min(1, b_kj / (A_k x)_j), max slack, lam.b and -lam.(Ax - b) at the
+// rho min_k min(1, b_kj / (A_k x)_j), with rho = min(1, M / sum x) for a
+// global-count row (1 without one), max slack, lam.b and -lam.(Ax - b) at the
 // FP32 point mu the pass used, and the Lagrangian sum over workgroups.
 //   out[0] = sum_w obj_part[w] - mu.b   (dual value g(mu))
 //   out[1] = max_r (A x - b)_r^+
 //   out[2] = -mu.(A x - b)
-__global__ void cert_items(const double* ax, const double* b, const float* mu, int m, int J, int eq_mask,
+__global__ void cert_items(const double* ax, const double* b, const float* mu, int m, int J, int eq_mask, int glob,
                            const double* obj_part, int n_wg, float* rfac, double* out) {
   __shared__ double sh[1024];
-  double lb = 0.0, slack = 0.0, lg = 0.0;
+  const int mJ = m * J;
+  double lb = 0.0, slack = 0.0, lg = 0.0, rho = 1.0;
+  if (glob) {
+    const double G = ax[mJ], M = b[mJ];
+    if (G > M) rho = M > 0.0 ? M / G : 0.0;
+    if (threadIdx.x == 0) {
+      slack = G - M;
+      lb = (double)mu[mJ] * M;
+      lg = -(double)mu[mJ] * (G - M);
+    }
+  }
   for (int j = threadIdx.x; j < J; j += blockDim.x) {
-    double rj = 1.0;
+    double rj = rho;
     for (int k = 0; k < m; ++k) {
       const int r = k * J + j;
       const double viol = ax[r] - b[r];
@@ -165,7 +177,7 @@ __global__ void cert_items(const double* ax, const double* b, const float* mu, i
       slack = fmax(slack, eq ? fabs(viol) : viol);
       lb += (double)mu[r] * b[r];
       lg -= (double)mu[r] * viol;
-      if (!eq && ax[r] > b[r]) rj = fmin(rj, b[r] > 0.0 ? b[r] / ax[r] : 0.0);
+      if (!eq && ax[r] > b[r]) rj = fmin(rj, b[r] > 0.0 ? rho * (b[r] / ax[r]) : 0.0);
     }
     rfac[j] = (float)rj;
   }
@@ -194,7 +206,7 @@ __global__ void cert_final(const double* pobj_part, int n_wg, double* out) {
 inline unsigned blocks_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 dl_status launch_reduce(const dl_problem* P) {
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   if (P->n_wg <= 0) return DL_OK;
   dim3 grid(blocks_for(mJ), (unsigned)((P->n_wg + DL_RED_ROWS - 1) / DL_RED_ROWS));
   hipLaunchKernelGGL(reduce_partials, grid, dim3(256), 0, P->stream, P->part, P->n_wg, mJ, P->acc);
@@ -227,6 +239,7 @@ upd_args make_upd(const dl_problem* P) {
   U.acc = P->acc;
   U.n_wg = P->n_wg;
   U.mJ = P->m * P->J;
+  U.nrow = (int)P->nrow();
   U.J = P->J;
   U.qs = P->qs_dev;
   U.eq_mask = P->eq_mask;
@@ -250,7 +263,7 @@ dl_status next_event_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, siz
 // Certificate at the solver's current lam (Table 4 metrics, certified gap).
 dl_status certificate(dl_solver* S, dl_solve_stats* st) {
   dl_problem* P = S->P;
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   DL_TRY(dl_launch_grad(P, M_HIST | M_OBJ, S->mu_lam, S->gamma, nullptr, nullptr, nullptr, P->obj_part));
   DL_TRY(launch_reduce(P));
   upd_args U = make_upd(P);
@@ -258,7 +271,7 @@ dl_status certificate(dl_solver* S, dl_solve_stats* st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
   DL_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(cert_items, dim3(1), dim3(1024), 0, P->stream, S->ax, P->b, S->mu_lam, P->m, P->J,
-                     P->eq_mask, P->obj_part, P->n_wg, P->rfac, P->cert_out);
+                     P->eq_mask, P->glob, P->obj_part, P->n_wg, P->rfac, P->cert_out);
   DL_HIP_TRY(hipGetLastError());
   DL_TRY(dl_launch_grad(P, M_REPAIR, S->mu_lam, S->gamma, P->rfac, nullptr, nullptr, P->pobj_part));
   hipLaunchKernelGGL(cert_final, dim3(1), dim3(1024), 0, P->stream, P->pobj_part, P->n_wg, P->cert_out);
@@ -296,7 +309,7 @@ extern "C" dl_status dl_dual_grad(dl_problem* P, const double* lambda, double ga
                                   float* x) {
   DL_CHECK_ARG(P && lambda, "NULL argument");
   DL_CHECK_ARG(gamma > 0.0 && isfinite(gamma), "gamma must be positive and finite");
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   hipLaunchKernelGGL(to_f32, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, lambda, mJ, P->mu);
   DL_HIP_TRY(hipGetLastError());
   const bool want_obj = dual_obj != nullptr;
@@ -309,7 +322,7 @@ extern "C" dl_status dl_dual_grad(dl_problem* P, const double* lambda, double ga
   DL_HIP_TRY(hipGetLastError());
   if (want_obj) {
     hipLaunchKernelGGL(cert_items, dim3(1), dim3(1024), 0, P->stream, P->lam_tmp, P->b, P->mu, P->m, P->J,
-                       P->eq_mask, P->obj_part, P->n_wg, P->rfac, P->cert_out);
+                       P->eq_mask, P->glob, P->obj_part, P->n_wg, P->rfac, P->cert_out);
     DL_HIP_TRY(hipGetLastError());
     DL_HIP_TRY(hipMemcpyAsync(P->cert_host, P->cert_out, sizeof(double), hipMemcpyDeviceToHost, P->stream));
     DL_HIP_TRY(hipStreamSynchronize(P->stream));
@@ -335,7 +348,7 @@ extern "C" dl_status dl_solver_create(dl_problem* P, const double* lambda0, dl_s
     return DL_ENOMEM;
   }
   S->P = P;
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   auto fail = [&](dl_status s) {
     dl_solver_destroy(S);
     return s;
@@ -397,7 +410,7 @@ extern "C" dl_status dl_solver_set_stage(dl_solver* S, double gamma, double step
   S->eta = step_scale * gamma / P->lhat;  // step proportional to gamma (L <= ||A'||^2/gamma)
   if (reset) {
     S->tk = 1.0;
-    const int mJ = P->m * P->J;
+    const int mJ = (int)P->nrow();  // dual rows
     hipLaunchKernelGGL(reset_momentum, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, P->D, mJ, S->lam, S->y,
                        S->mu_y);
     DL_HIP_TRY(hipGetLastError());
@@ -408,7 +421,7 @@ extern "C" dl_status dl_solver_set_stage(dl_solver* S, double gamma, double step
 extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
   DL_CHECK_ARG(S && n >= 0, "bad argument");
   dl_problem* P = S->P;
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   upd_args U = make_upd(P);
   U.lam = S->lam;
   U.y = S->y;
@@ -459,7 +472,7 @@ __global__ void state_gather_points(const double* D, int mJ, const double* lam, 
 extern "C" dl_status dl_solver_export(dl_solver* S, double* state, dl_solver_meta* meta) {
   DL_CHECK_ARG(S && state && meta, "NULL argument");
   dl_problem* P = S->P;
-  const size_t mJ = (size_t)P->m * P->J;
+  const size_t mJ = (size_t)P->nrow();  // dual rows
   DL_HIP_TRY(hipMemcpyAsync(state, S->lam, sizeof(double) * mJ, hipMemcpyDeviceToDevice, P->stream));
   DL_HIP_TRY(hipMemcpyAsync(state + mJ, S->y, sizeof(double) * mJ, hipMemcpyDeviceToDevice, P->stream));
   meta->gamma = S->gamma;
@@ -473,7 +486,7 @@ extern "C" dl_status dl_solver_export(dl_solver* S, double* state, dl_solver_met
 extern "C" dl_status dl_solver_import(dl_solver* S, const double* state, const dl_solver_meta* meta) {
   DL_CHECK_ARG(S && state && meta, "NULL argument");
   dl_problem* P = S->P;
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   DL_CHECK_ARG(meta->m_times_j == mJ, "state was exported from a problem of another size");
   DL_CHECK_ARG(meta->gamma > 0.0 && isfinite(meta->gamma) && meta->eta > 0.0 && isfinite(meta->eta) &&
                    meta->tk >= 1.0 && isfinite(meta->tk) && meta->iters >= 0,
@@ -493,7 +506,7 @@ extern "C" dl_status dl_solver_import(dl_solver* S, const double* state, const d
 extern "C" dl_status dl_solver_get_lambda(dl_solver* S, double* out) {
   DL_CHECK_ARG(S && out, "NULL argument");
   dl_problem* P = S->P;
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   hipLaunchKernelGGL(scaled_to_units, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, P->D, mJ, S->lam, out);
   DL_HIP_TRY(hipGetLastError());
   return DL_OK;
@@ -556,7 +569,7 @@ dl_status measure_pass(dl_solver* S, int reps, double* ms, std::vector<double>* 
   P->clocking = false;
   if (rc == DL_OK && hipEventRecord(e1, P->stream) != hipSuccess) rc = DL_EHIP;
   if (rc == DL_OK &&
-      hipMemsetAsync(P->acc, 0, sizeof(unsigned long long) * (size_t)P->m * P->J, P->stream) != hipSuccess)
+      hipMemsetAsync(P->acc, 0, sizeof(unsigned long long) * (size_t)P->nrow(), P->stream) != hipSuccess)
     rc = DL_EHIP;
   std::vector<unsigned long long> clk(2 * (size_t)std::max(P->n_wg, 1));
   if (rc == DL_OK && P->n_wg > 0 &&
@@ -809,9 +822,9 @@ extern "C" dl_status dl_solve_noalloc(dl_problem* P, const dl_solve_opts* o, con
   DL_CHECK_ARG(P && o && st && lambda_out, "NULL argument");
   DL_TRY(check_schedule(o));
   DL_CHECK_ARG(o->autotune_rounds == 0, "dl_solve_noalloc does not run the workgroup tuner (autotune_rounds must be 0)");
-  const int64_t mJ = (int64_t)P->m * P->J;
+  const int64_t mJ = P->nrow();  // dual rows
   if (mJ > DL_NOALLOC_MAX_MJ) {
-    dl_set_error("dl_solve_noalloc: n_families * n_items exceeds its fixed state array (16384 rows)");
+    dl_set_error("dl_solve_noalloc: the problem's dual rows exceed its fixed state array (16384 rows)");
     return DL_EUNSUPPORTED;
   }
   int dev = -1;
@@ -873,7 +886,7 @@ extern "C" dl_status dl_solve_warm(dl_problem* P, const dl_solve_opts* o, int32_
                                    int32_t* chosen, double* cand_dual) {
   DL_CHECK_ARG(P && o && stats && lambda_out && n_cand >= 1 && cands, "bad argument");
   DL_CHECK_ARG(o->n_stages >= 1 && o->gammas, "empty schedule");
-  const int mJ = P->m * P->J;
+  const int mJ = (int)P->nrow();  // dual rows
   const double gamma0 = o->gammas[0];
   double* tmp = nullptr;
   int* bad = nullptr;

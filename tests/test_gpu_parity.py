@@ -653,3 +653,95 @@ def test_tuned_batch_matches_solo(dl, wl):
     assert batch.tune()["rounds"] == 0
     for k in range(len(members)):
         assert np.array_equal(lam_u[k].cpu().numpy(), lam_b[k].cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# Global-count coupling row (Section 5): sum over all (i, j) of x_ij <= M
+# ---------------------------------------------------------------------------
+def _global_cases(wl):
+    import dataclasses
+    out = {}
+    base = wl.tiny_plain(seed=2, binding=True, n_users=8000, n_items=80)
+    out["simplex"] = (dataclasses.replace(base, global_cap=0.3 * base.n_users), 1e-2)
+    b2 = wl.random_small(60, 6000, 200, 150, n_families=2, a_ones=False, proj="box", b_scale=0.4)
+    out["box_stored_a"] = (dataclasses.replace(b2, global_cap=0.5 * b2.nnz * 0.2), 2e-2)
+    b3 = wl.random_small(61, 3000, 3500, 3000, proj="boxcut", radius=2.0, upper=0.25, b_scale=0.3)
+    out["boxcut_long_rows"] = (dataclasses.replace(b3, global_cap=0.4 * b3.n_users), 5e-2)
+    return out
+
+
+@pytest.mark.parametrize("name", ["simplex", "box_stored_a", "boxcut_long_rows"])
+def test_global_count_dual_grad_matches_oracle(dl, orc, wl, name):
+    import torch
+    inst, gamma = _global_cases(wl)[name]
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    assert prob.nrow == inst.n_families * inst.n_items + 1
+    lam = _lam_point(orc, inst, gamma, 2)
+    lam32 = lam.astype(np.float32).astype(np.float64)
+    assert lam32[-1] > 0, "the cap binds at this point"
+    g, grad, x = prob.dual_grad(torch.from_numpy(lam), gamma, want_obj=True, want_x=True)
+    grad, x = grad.cpu().numpy(), x.cpu().numpy()
+    go, grad_o, x_o, ax_o = orc.dual_grad(inst, lam32, gamma)
+    # v carries the global dual: max|v| per row from the oracle's x-independent formula
+    a = inst.a_dense().astype(np.float64)
+    s = np.full(inst.nnz, lam32[-1])
+    for k in range(inst.n_families):
+        s += a[k] * lam32[k * inst.n_items + inst.item_idx]
+    vabs = np.abs(inst.c.astype(np.float64) + s) / gamma
+    vmax_el = np.repeat(np.maximum.reduceat(vabs, inst.row_ptr[:-1]), inst.degrees())
+    xtol = 32 * U32 * np.maximum(vmax_el, 1.0)
+    assert np.all(np.abs(x - x_o) <= xtol), float((np.abs(x - x_o) / xtol).max())
+    qs = np.array(prob.info()["qscale"], dtype=np.float64)
+    J, mJ = inst.n_items, inst.n_families * inst.n_items
+    for k in range(inst.n_families):
+        bound = np.bincount(inst.item_idx, weights=np.abs(a[k]) * (xtol + 1.0 / qs[k]), minlength=J)
+        assert np.all(np.abs(grad[k * J:(k + 1) * J] - grad_o[k * J:(k + 1) * J]) <= bound + 1e-12), k
+    # the global entry: sum of all x on a grid no coarser than 2^(30 - ceil log2 radius)
+    qg = 2.0 ** (30 - np.ceil(np.log2(inst.radius)))
+    gb = float(np.sum(xtol + 1.0 / qg))
+    print(f"{name}: global grad {grad[mJ]:.6f} vs {grad_o[mJ]:.6f} (bound {gb:.2e}); dual {g:.9g} vs {go:.9g}")
+    assert abs(grad[mJ] - grad_o[mJ]) <= gb
+    assert abs(g - go) <= 2e-6 * max(1.0, abs(go))
+
+
+@pytest.mark.parametrize("name", ["simplex", "box_stored_a"])
+def test_global_count_trajectory_and_certificate(dl, orc, wl, name):
+    """Continuation gamma 0.1 -> 0.01 (150 iterations each, Jacobi, the Weyl step
+    bound): lam, including the global dual, within 1e-5 of the oracle; then the
+    certificate (with the global repair factor) at the final point."""
+    import torch
+    inst, _ = _global_cases(wl)[name]
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    D, L = orc.scaling(inst, jacobi=True)
+    assert abs(prob.info()["lhat"] - L) <= 1e-9 * L
+    sched = dict(gammas=[1e-1, 1e-2], iters=[150, 150])
+    lam, _ = prob.solve(**sched, check_every=0)
+    lo, _, _, _ = orc.solve(inst, sched["gammas"], sched["iters"], jacobi=True, check_every=0)
+    assert lo[-1] > 0
+    _lam_close(lam.cpu().numpy(), lo, what=f"global-count {name}")
+    lam32 = lo.astype(np.float32).astype(np.float64)
+    s = prob.solver(torch.from_numpy(lam32))
+    s.set_stage(1e-2, 1.0, True)
+    cg = s.certificate()
+    co = orc.certificate(inst, lam32, 1e-2)
+    g, P = co["dual_obj"], co["primal_obj"]
+    print(f"certificate: gpu {cg}; oracle {co}")
+    assert abs(cg["dual_obj"] - g) <= 2e-6 * max(1.0, abs(g))
+    assert abs(cg["primal_obj"] - P) <= 4e-6 * max(1.0, abs(P))
+    assert abs(cg["rel_gap"] - co["rel_gap"]) <= 6e-6 * max(1.0, abs(P)) / max(1.0, abs(g))
+    assert cg["rel_gap"] >= -1e-6
+
+
+def test_global_count_batch_member_matches_solo(dl, wl):
+    import dataclasses
+    members = []
+    for k in range(3):
+        m = wl.tiny_plain(seed=70 + k, binding=True, n_users=3000 + 1500 * k, n_items=60)
+        members.append(dataclasses.replace(m, global_cap=0.35 * m.n_users) if k != 1 else m)
+    sched = dict(gammas=[1e-1, 1e-2], iters=[80, 80], check_every=0)
+    probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]
+    lam_b, _ = dl.Batch(probs).solve(**sched)
+    for k, p in enumerate(probs):
+        lam_s, _ = p.solve(**sched)
+        assert lam_b[k].numel() == p.nrow
+        assert np.array_equal(lam_b[k].cpu().numpy(), lam_s.cpu().numpy()), k
