@@ -94,6 +94,7 @@ struct dl_batch {
   size_t part_cap = 0;
   int n_wg = 0, n_blk = 0;
   size_t lds = 0;
+  bool glob = false;  // some live member has a global-count row
   // host mirrors
   std::vector<dl_grad_args> h_args;
   std::vector<dl_wg_desc> h_wgs;
@@ -234,6 +235,8 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
   B->n_wg = (int)B->h_wgs.size();
   B->n_blk = (int)B->h_blk.size();
   B->lds = lds;
+  B->glob = false;
+  for (int i : live) B->glob = B->glob || B->probs[i]->glob;
   if (B->d_wgs) DL_HIP_TRY(hipFree(B->d_wgs));
   if (B->d_upd) DL_HIP_TRY(hipFree(B->d_upd));
   if (B->d_blk) DL_HIP_TRY(hipFree(B->d_blk));
@@ -293,7 +296,8 @@ static dl_status measure_batch(dl_batch* B, int reps, double* ms, std::vector<do
   if (hipEventRecord(e0, B->stream) != hipSuccess) rc = DL_EHIP;
   for (int r = 0; r < reps && rc == DL_OK; ++r) {
     rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
-    if (rc == DL_OK) rc = dl_launch_grad_batch(B->probs[B->live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream);
+    if (rc == DL_OK)
+      rc = dl_launch_grad_batch(B->probs[B->live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream, B->glob);
   }
   if (rc == DL_OK && hipEventRecord(e1, B->stream) != hipSuccess) rc = DL_EHIP;
   std::vector<unsigned long long> clk(need);
@@ -536,7 +540,7 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
     while ((n_it < 0 || k < n_it) && total < o->max_iters && !live.empty()) {
       rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
       if (rc != DL_OK) break;
-      rc = dl_launch_grad_batch(B->probs[live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream);
+      rc = dl_launch_grad_batch(B->probs[live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream, B->glob);
       if (rc != DL_OK) break;
       const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
       const double beta = (tk - 1.0) / tn;

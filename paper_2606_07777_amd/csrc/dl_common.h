@@ -91,6 +91,7 @@ enum : int {
   M_REPAIR = 4,  // accumulate c.x~ + gamma/2 x~^2 with x~ = r_j x (certificate)
   M_VIN = 8,     // v given in caller order (ProjectionMap), no gather
   M_XOUT = 16,   // write x in the caller's order
+  M_GLOB = 32,   // with M_HIST: also count sum x for the global-count row
 };
 
 struct dl_grad_args {
@@ -208,8 +209,9 @@ dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamm
 // Task ranges of n_wg workgroups with equal cost-model weight.
 std::vector<int64_t> dl_model_partition(const dl_problem* P, int n_wg);
 dl_status dl_set_partition(dl_problem* P, const std::vector<int64_t>& bounds);
+// glob: some member has a global-count row (runs the kernel that also counts sum x)
 dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
-                               size_t lds, hipStream_t st);
+                               size_t lds, hipStream_t st, bool glob);
 dl_status dl_grad_prepare(const dl_problem* P);
 // Fixed-point scales for a histogram pass at gather point mu (into P->qs_dev),
 // and the same for every instance of a batched pass (one block per entry).

@@ -36,7 +36,7 @@
 #define DL_GV_DECL(mf, a, bf)                                                                              \
   dl_status dl_grad_launch_v_##mf##_##a##_##bf(const dl_problem*, int, const dl_grad_args&, size_t);       \
   dl_status dl_grad_batch_v_##mf##_##a##_##bf(const dl_problem*, int, const dl_grad_args*, const dl_wg_desc*, \
-                                              size_t, hipStream_t);                                         \
+                                              size_t, hipStream_t, bool);                                   \
   void dl_grad_attr_v_##mf##_##a##_##bf();
 DL_GV_DECL(1, 0, 0)
 DL_GV_DECL(1, 0, 1)
@@ -185,17 +185,17 @@ dl_status dl_grad_prepare(const dl_problem* P) {
 }
 
 dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
-                               size_t lds, hipStream_t st) {
+                               size_t lds, hipStream_t st, bool glob) {
   if (n_wg <= 0) return DL_OK;
   const bool bf = P->storage == DL_BF16;
   if (P->mf == 1 && !P->has_a)
-    return bf ? dl_grad_batch_v_1_0_1(P, n_wg, d_args, d_wgs, lds, st)
-              : dl_grad_batch_v_1_0_0(P, n_wg, d_args, d_wgs, lds, st);
+    return bf ? dl_grad_batch_v_1_0_1(P, n_wg, d_args, d_wgs, lds, st, glob)
+              : dl_grad_batch_v_1_0_0(P, n_wg, d_args, d_wgs, lds, st, glob);
   if (P->mf == 1)
-    return bf ? dl_grad_batch_v_1_1_1(P, n_wg, d_args, d_wgs, lds, st)
-              : dl_grad_batch_v_1_1_0(P, n_wg, d_args, d_wgs, lds, st);
-  return bf ? dl_grad_batch_v_4_1_1(P, n_wg, d_args, d_wgs, lds, st)
-            : dl_grad_batch_v_4_1_0(P, n_wg, d_args, d_wgs, lds, st);
+    return bf ? dl_grad_batch_v_1_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
+              : dl_grad_batch_v_1_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
+  return bf ? dl_grad_batch_v_4_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
+            : dl_grad_batch_v_4_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
 }
 
 dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamma) {
@@ -235,6 +235,7 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
                          const float* v_in, float* x_out, double* obj_part, bool scaled) {
   if (P->n_wg <= 0) return DL_OK;
   if (x_out) mode |= M_XOUT;
+  if (P->glob && (mode & M_HIST)) mode |= M_GLOB;
   if ((mode & M_HIST) && !scaled) DL_TRY(dl_launch_qscale(P, mu, gamma));
   dl_grad_args A = dl_make_grad_args(P, mu, gamma);
   A.rfac = rfac;

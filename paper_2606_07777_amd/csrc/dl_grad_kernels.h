@@ -518,7 +518,7 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
           }
         }
         // global-count row: x >= 0 on its own grid, summed per lane in 64 bits
-        if (A.glob) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
+        if constexpr ((MODE & M_GLOB) != 0) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
       }
       if constexpr ((MODE & M_OBJ) != 0) {
         // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
@@ -762,7 +762,7 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
           else hist_add_pos(s_hist, f * 8 * A.J + 2 * j, w, qs[f]);
         }
       }
-      if (A.glob) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
+      if constexpr ((MODE & M_GLOB) != 0) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
     }
     if constexpr ((MODE & M_OBJ) != 0) lobj += x > 0.f ? x * fmaf(0.5f * A.gamma, x, -A.gamma * v) : 0.f;
     if constexpr ((MODE & M_REPAIR) != 0) {
@@ -843,7 +843,7 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
     for (int o = 32; o > 0; o >>= 1) o_ += __shfl_xor(o_, o, 64);
     if (lane == 0) s_obj[wave] = o_;
   }
-  if ((MODE & M_HIST) && A.glob) {
+  if ((MODE & M_GLOB) && A.glob) {
     // integer sums: exact in any order
     unsigned long long g_ = acc.gcnt;
     for (int o = 32; o > 0; o >>= 1) g_ += __shfl_xor(g_, o, 64);
@@ -853,7 +853,7 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
   if (MODE & M_HIST) {
     unsigned long long* dst = A.part + (size_t)slot * nrow;
     for (int r = tid; r < mJ; r += DL_WG) dst[r] = s_hist[r];
-    if (A.glob && tid == 0) {
+    if ((MODE & M_GLOB) && A.glob && tid == 0) {
       unsigned long long g_ = 0ull;
       for (int w = 0; w < DL_WAVES; ++w) g_ += s_gc[w];
       dst[mJ] = g_;
@@ -901,6 +901,11 @@ dl_status launch_mode(const dl_problem* P, int mode, const dl_grad_args& A, size
     case M_HIST | M_OBJ: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ>(P, A, lds);
     case M_HIST | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT>(P, A, lds);
     case M_HIST | M_OBJ | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT>(P, A, lds);
+    case M_HIST | M_GLOB: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB>(P, A, lds);
+    case M_HIST | M_OBJ | M_GLOB: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_GLOB>(P, A, lds);
+    case M_HIST | M_XOUT | M_GLOB: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT | M_GLOB>(P, A, lds);
+    case M_HIST | M_OBJ | M_XOUT | M_GLOB:
+      return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB>(P, A, lds);
     case M_REPAIR: return launch_one<MF, HAS_A, KMAX, TV, M_REPAIR>(P, A, lds);
     case M_VIN | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_VIN | M_XOUT>(P, A, lds);
     default: dl_set_error("internal: unknown gradient-pass mode"); return DL_EINVAL;
@@ -909,9 +914,14 @@ dl_status launch_mode(const dl_problem* P, int mode, const dl_grad_args& A, size
 
 template <int MF, bool HAS_A, int KMAX, typename TV>
 dl_status launch_batch_t(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
-                         size_t lds, hipStream_t st) {
+                         size_t lds, hipStream_t st, bool glob) {
   (void)P;
-  hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST>), dim3(n_wg), dim3(DL_WG), lds, st, d_args, d_wgs);
+  if (glob)
+    hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB>), dim3(n_wg), dim3(DL_WG), lds, st,
+                       d_args, d_wgs);
+  else
+    hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST>), dim3(n_wg), dim3(DL_WG), lds, st, d_args,
+                       d_wgs);
   DL_HIP_TRY(hipGetLastError());
   return DL_OK;
 }
@@ -930,6 +940,16 @@ void set_attr_all() {
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_GLOB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT | M_GLOB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 }  // namespace
