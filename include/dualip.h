@@ -128,6 +128,7 @@ typedef struct {
   int64_t bucket_users[8];
   float qscale[4];            /* fixed-point step of each family's accumulation is 1/qscale */
   int64_t n_rows;             /* dual coordinates: m*J (+1 with the global-count row) */
+  int32_t n_windows;          /* launches per gradient pass: 1, or the histogram row windows */
 } dl_problem_info;
 
 /*
@@ -136,8 +137,15 @@ typedef struct {
  * step bound lhat (Appendix C), and copies c and a into library storage.
  * Returns DL_EINVAL for malformed data (non-monotone row_ptr, item out of
  * range or repeated in a row, non-finite c/a/b, radius <= 0, a negative or
- * non-finite global_cap), DL_EUNSUPPORTED when m*J exceeds the on-chip
- * accumulation capacity (13,000), DL_ENOMEM or DL_EHIP otherwise.
+ * non-finite global_cap), DL_EUNSUPPORTED when J > 16,383 (16-bit item
+ * offsets) or n_rows + J > 40,832 (the duals and one repair factor per item
+ * staged in one workgroup's 160 KiB of LDS), DL_ENOMEM or DL_EHIP otherwise.
+ * Up to m*J = 13,000 each workgroup accumulates all of A x in LDS in one
+ * launch.  Beyond that the histogram rows are cut into n_windows equal windows
+ * that fit in LDS beside the duals, and a gradient pass is one launch per
+ * window: each recomputes x and keeps the sums of its own rows (the result is
+ * bitwise the same; the data is read n_windows times).  Such problems use the
+ * four-family kernel and cannot join a batch.
  * Synchronises the stream before returning.
  */
 dl_status dl_problem_create(const dl_problem_desc* desc, dl_problem** out);
@@ -290,14 +298,15 @@ void dl_batch_destroy(dl_batch* batch); /* NULL-safe; does not destroy the probl
  * iteration is one gradient-pass launch over all live members (workgroups
  * dealt by pass cost) plus one update launch.  Members leave the launch when
  * their certified gap reaches tol at a check point of the final stage.
- * With opts->autotune_rounds > 0 the pass cost is measured once, after up to
- * 50 iterations of the first stage: for grids of 1, 2 and 4 workgroups per
- * compute unit, the batched pass is timed with per-workgroup clock stamps and
- * the workgroups are re-dealt (between members and inside each) from the
- * measured times that many times; the faster of the best configuration found
- * and the starting one (cost model, 4 per compute unit) is kept for the rest
- * of the solve (dl_batch_get_tune reports it).  The split never changes a
- * member's iterates: they stay bitwise equal to its solo solve.
+ * With opts->autotune_rounds = r > 0 the workgroup schedule is tuned on the
+ * solve's own iterations (no extra passes), from iteration 10 of the first
+ * stage that runs at least 10 + 12 (1 + r) iterations: for grids of 4, 2 and
+ * 1 workgroups per compute unit, the cost-model split and then r splits
+ * re-dealt (between members and inside each) from the previous trial's
+ * per-workgroup clock stamps each serve 4 iterations timed with HIP events;
+ * the fastest serves the rest of the solve (dl_batch_get_tune reports it).
+ * The split never changes a member's iterates: they stay bitwise equal to its
+ * solo solve.
  *   lambda0     host array of n device pointers (n_rows of member i each), or NULL (zeros)
  *   lambda_out  host array of n device pointers (n_rows of member i each)
  *   stats       host array of n records (iters and status per member)
@@ -331,9 +340,11 @@ typedef struct {
 dl_status dl_solver_autotune(dl_solver* s, int32_t rounds, dl_tune_result* out);
 /*
  * The tuning of the last dl_batch_solve run on this batch (all zeros when it
- * ran without autotune_rounds).  Here pass_ms_* is the mean time of one
- * batched gradient pass with its fixed-point scale pass (10 passes each), and
- * n_workgroups the grid of the kept split over the members live when tuned.
+ * ran without autotune_rounds).  Here pass_ms_model is the mean time of one
+ * whole iteration (scale pass, batched gradient pass, update) over the first
+ * trial (cost-model split, 4 workgroups per compute unit), pass_ms_tuned the
+ * same over the kept configuration's trial, and n_workgroups the kept grid
+ * over the members live when tuned.
  */
 dl_status dl_batch_get_tune(const dl_batch* batch, dl_tune_result* out);
 

@@ -85,6 +85,7 @@ class dl_problem_info(ctypes.Structure):
         ("bucket_users", ctypes.c_int64 * 8),
         ("qscale", ctypes.c_float * 4),
         ("n_rows", ctypes.c_int64),
+        ("n_windows", ctypes.c_int32),
     ]
 
 

@@ -270,53 +270,16 @@ static dl_status set_clocking(dl_batch* B, bool on) {
   return DL_OK;
 }
 
-// Times `reps` batched gradient passes (scale pass included) at the current
-// gather points and reads back every workgroup's duration of the last one.
-// The passes only rewrite the partial slots that the next iteration's pass
-// rewrites anyway, so the solver states are unchanged.
-static dl_status measure_batch(dl_batch* B, int reps, double* ms, std::vector<double>* dur) {
-  const size_t need = 2 * (size_t)std::max(B->n_wg, 1);
-  if (need > B->clock_cap) {
-    DL_HIP_TRY(hipStreamSynchronize(B->stream));
-    if (B->d_clock) DL_HIP_TRY(hipFree(B->d_clock));
-    B->d_clock = nullptr;
-    B->clock_cap = 0;
-    DL_HIP_TRY(hipMalloc((void**)&B->d_clock, need * sizeof(unsigned long long)));
-    B->clock_cap = need;
-  }
-  DL_TRY(set_clocking(B, true));
-  hipEvent_t e0, e1;
-  DL_HIP_TRY(hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    dl_set_error("hipEventCreate failed");
-    return DL_EHIP;
-  }
-  dl_status rc = DL_OK;
-  if (hipEventRecord(e0, B->stream) != hipSuccess) rc = DL_EHIP;
-  for (int r = 0; r < reps && rc == DL_OK; ++r) {
-    rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
-    if (rc == DL_OK)
-      rc = dl_launch_grad_batch(B->probs[B->live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream, B->glob);
-  }
-  if (rc == DL_OK && hipEventRecord(e1, B->stream) != hipSuccess) rc = DL_EHIP;
-  std::vector<unsigned long long> clk(need);
-  if (rc == DL_OK && hipMemcpyAsync(clk.data(), B->d_clock, sizeof(unsigned long long) * 2 * B->n_wg,
-                                    hipMemcpyDeviceToHost, B->stream) != hipSuccess)
-    rc = DL_EHIP;
-  if (rc == DL_OK && hipStreamSynchronize(B->stream) != hipSuccess) rc = DL_EHIP;
-  float t = 0.f;
-  if (rc == DL_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = DL_EHIP;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rc != DL_OK) {
-    dl_set_error("timing a batched gradient pass failed");
-    return rc;
-  }
-  DL_TRY(set_clocking(B, false));
-  *ms = t / reps;
-  dur->assign((size_t)B->n_wg, 0.0);
-  for (int w = 0; w < B->n_wg; ++w) (*dur)[(size_t)w] = (double)(clk[2 * (size_t)w + 1] - clk[2 * (size_t)w]);
+// Grows the clock-stamp buffer to two entries per workgroup of the largest grid
+// the tuner tries.
+static dl_status ensure_clock(dl_batch* B, size_t need) {
+  if (need <= B->clock_cap) return DL_OK;
+  DL_HIP_TRY(hipStreamSynchronize(B->stream));
+  if (B->d_clock) DL_HIP_TRY(hipFree(B->d_clock));
+  B->d_clock = nullptr;
+  B->clock_cap = 0;
+  DL_HIP_TRY(hipMalloc((void**)&B->d_clock, need * sizeof(unsigned long long)));
+  B->clock_cap = need;
   return DL_OK;
 }
 
@@ -351,80 +314,119 @@ static double wg_imbalance(const std::vector<double>& d) {
   return sum > 0 ? mx / (sum / (double)d.size()) : 1.0;
 }
 
-// Re-deals the workgroups of the live instances from measured time.  For
-// grids of 1, 2 and 4 workgroups per compute unit, the batched pass is timed
-// from the cost-model split and the split is rebuilt from the measured profile
-// `rounds` times.  The fastest configuration found is timed again against the
-// starting one (cost model, 4 per compute unit) with more passes, and the
-// faster of the two is kept for the rest of the solve.
-static dl_status tune_batch(dl_batch* B, double gamma, int rounds) {
-  const int reps = 3, final_reps = 10;
-  const std::vector<int> live = B->live;
-  const std::vector<dl_inst_profile> start = B->prof;
-  const int start_wpc = B->wg_per_cu;
-  dl_tune_result& out = B->tune;
-  memset(&out, 0, sizeof(out));
-  out.rounds = rounds;
-  double ms;
-  std::vector<double> dur;
-  std::vector<dl_inst_profile> best = start;
-  int best_wpc = start_wpc;
+// The batch tuner.  It times the solve's own iterations, so it costs no extra
+// gradient passes: each trial configuration serves kTrialIters consecutive
+// iterations with per-workgroup clock stamps on and HIP events around them.
+// The trials are, for grids of 4, 2 and 1 workgroups per compute unit, the
+// cost-model split followed by `rounds` splits re-dealt from the previous
+// trial's measured workgroup times.  After the last trial the fastest
+// configuration serves the rest of the solve.  A split never changes an
+// iterate, so the trials differ only in time per iteration.
+struct loop_tuner {
+  static constexpr int kTrialIters = 4;
+  static constexpr int kGrids = 3;
+  static int grid_wpc(int g) { return 4 >> g; }
+  int rounds = 0;
+  bool running = false;
+  int grid = 0, round = 0, left = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<dl_inst_profile> start, best;
+  int best_wpc = 4;
   double best_ms = 1e300, best_imb = 1.0;
-  bool improved = false;
-  for (int wpc = 1; wpc <= 4; wpc *= 2) {
-    B->wg_per_cu = wpc;
-    B->prof = start;
-    DL_TRY(build_tables(B, live, gamma));
-    DL_TRY(measure_batch(B, reps, &ms, &dur));
-    if (wpc == start_wpc) out.imbalance_model = wg_imbalance(dur);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best_imb = wg_imbalance(dur);
-      best = start;
-      best_wpc = wpc;
-      improved = wpc != start_wpc;
-    }
-    for (int r = 0; r < rounds; ++r) {
-      const std::vector<dl_inst_profile> used = profile_of(B, dur);
-      B->prof = used;
-      DL_TRY(build_tables(B, live, gamma));
-      DL_TRY(measure_batch(B, reps, &ms, &dur));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best_imb = wg_imbalance(dur);
-        best = used;
-        best_wpc = wpc;
-        improved = true;
-      }
-    }
+  // iterations one tuning takes
+  static int64_t span(int rounds) { return (int64_t)kGrids * (1 + rounds) * kTrialIters; }
+  ~loop_tuner() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   }
-  // the starting configuration and the best one, timed again with more passes
-  // (when nothing beat the start, it is kept without a second timing)
-  B->wg_per_cu = start_wpc;
-  B->prof = start;
-  DL_TRY(build_tables(B, live, gamma));
-  DL_TRY(measure_batch(B, final_reps, &ms, &dur));
-  out.pass_ms_model = ms;
-  double kept_ms = ms;
-  out.imbalance_tuned = out.imbalance_model;
-  if (improved) {
-    B->wg_per_cu = best_wpc;
-    B->prof = best;
-    DL_TRY(build_tables(B, live, gamma));
-    double ms_b;
-    DL_TRY(measure_batch(B, final_reps, &ms_b, &dur));
-    if (ms_b < ms) {
-      kept_ms = ms_b;
-      out.imbalance_tuned = best_imb;
-    } else {
-      B->wg_per_cu = start_wpc;
-      B->prof = start;
-      DL_TRY(build_tables(B, live, gamma));
-    }
-  }
-  out.pass_ms_tuned = kept_ms;
-  out.n_workgroups = B->n_wg;
+};
+
+// Builds the tables of the current trial configuration and starts its timing.
+static dl_status trial_begin(dl_batch* B, loop_tuner& T, double gamma) {
+  DL_TRY(build_tables(B, B->live, gamma));
+  DL_TRY(set_clocking(B, true));
+  DL_HIP_TRY(hipEventRecord(T.e0, B->stream));
+  T.left = loop_tuner::kTrialIters;
   return DL_OK;
+}
+
+static dl_status tuner_start(dl_batch* B, loop_tuner& T, double gamma, int rounds) {
+  memset(&B->tune, 0, sizeof(B->tune));
+  T.rounds = rounds;
+  if (!T.e0) DL_HIP_TRY(hipEventCreate(&T.e0));
+  if (!T.e1) DL_HIP_TRY(hipEventCreate(&T.e1));
+  DL_TRY(ensure_clock(B, 2 * (size_t)std::max<int>((int)B->live.size(), B->n_cu * loop_tuner::grid_wpc(0))));
+  T.start = B->prof;
+  T.best = B->prof;
+  T.best_wpc = B->wg_per_cu;
+  T.best_ms = 1e300;
+  T.grid = 0;
+  T.round = 0;
+  B->wg_per_cu = loop_tuner::grid_wpc(0);
+  T.running = true;
+  return trial_begin(B, T, gamma);
+}
+
+// Ends the current trial (after its last iteration was enqueued): reads its
+// time and workgroup durations, then starts the next trial or keeps the best.
+static dl_status trial_end(dl_batch* B, loop_tuner& T, double gamma) {
+  DL_HIP_TRY(hipEventRecord(T.e1, B->stream));
+  std::vector<unsigned long long> clk(2 * (size_t)B->n_wg);
+  if (B->n_wg > 0)
+    DL_HIP_TRY(hipMemcpyAsync(clk.data(), B->d_clock, sizeof(unsigned long long) * clk.size(), hipMemcpyDeviceToHost,
+                              B->stream));
+  DL_HIP_TRY(hipStreamSynchronize(B->stream));
+  float t = 0.f;
+  DL_HIP_TRY(hipEventElapsedTime(&t, T.e0, T.e1));
+  const double ms = (double)t / loop_tuner::kTrialIters;
+  std::vector<double> dur((size_t)B->n_wg);
+  for (size_t w = 0; w < dur.size(); ++w) dur[w] = (double)(clk[2 * w + 1] - clk[2 * w]);
+  const double imb = wg_imbalance(dur);
+  dl_tune_result& out = B->tune;
+  if (T.grid == 0 && T.round == 0) {
+    out.pass_ms_model = ms;
+    out.imbalance_model = imb;
+  }
+  if (ms < T.best_ms) {
+    T.best_ms = ms;
+    T.best_imb = imb;
+    T.best = B->prof;
+    T.best_wpc = B->wg_per_cu;
+  }
+  if (T.round < T.rounds) {
+    B->prof = profile_of(B, dur);
+    ++T.round;
+  } else if (T.grid + 1 < loop_tuner::kGrids) {
+    ++T.grid;
+    T.round = 0;
+    B->wg_per_cu = loop_tuner::grid_wpc(T.grid);
+    B->prof = T.start;
+  } else {
+    T.running = false;
+    B->wg_per_cu = T.best_wpc;
+    B->prof = T.best;
+    DL_TRY(build_tables(B, B->live, gamma));
+    out.rounds = T.rounds;
+    out.pass_ms_tuned = T.best_ms;
+    out.imbalance_tuned = T.best_imb;
+    out.n_workgroups = B->n_wg;
+    return DL_OK;
+  }
+  return trial_begin(B, T, gamma);
+}
+
+// Stops a tuning that the live set changed under: the best configuration
+// timed so far (or the one running) serves on; build_tables follows.
+static void tuner_abort(dl_batch* B, loop_tuner& T) {
+  if (!T.running) return;
+  T.running = false;
+  if (T.best_ms < 1e300) {
+    B->wg_per_cu = T.best_wpc;
+    B->prof = T.best;
+    B->tune.rounds = T.rounds;
+    B->tune.pass_ms_tuned = T.best_ms;
+    B->tune.imbalance_tuned = T.best_imb;
+  }
 }
 
 extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_batch** out) {
@@ -432,6 +434,11 @@ extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_bat
   *out = nullptr;
   DL_CHECK_ARG(n >= 1 && probs, "need at least one problem");
   for (int i = 0; i < n; ++i) DL_CHECK_ARG(probs[i], "NULL problem in batch");
+  for (int i = 0; i < n; ++i)
+    if (probs[i]->tile_rows > 0) {
+      dl_set_error("batch members must hold their whole histogram in one window (n_families * n_items <= 13000)");
+      return DL_EUNSUPPORTED;
+    }
   // each member keeps per-pass state (fixed-point scales, partial slots) in its problem
   for (int i = 0; i < n; ++i)
     for (int k = i + 1; k < n; ++k) DL_CHECK_ARG(probs[i] != probs[k], "a problem appears twice in the batch");
@@ -521,6 +528,9 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
   std::vector<int> last_stage(B->n, 0);
   dl_status rc = DL_OK;
   int64_t total = 0;
+  constexpr int64_t kTuneStart = 10;
+  loop_tuner tuner;
+  bool tuned = false;
   for (int stage = 0; stage < o->n_stages && rc == DL_OK && !live.empty(); ++stage) {
     const double gamma = o->gammas[stage];
     for (int i : live) {
@@ -535,9 +545,18 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
     const int64_t n_it = o->iters[stage];
     double tk = 1.0;
     int64_t k = 0;
-    // the tuner runs once, after up to 50 iterations of the first stage
-    const int64_t tune_at = (stage == 0 && o->autotune_rounds > 0) ? (n_it < 0 ? 50 : std::min<int64_t>(n_it, 50)) : -1;
+    // the tuner runs once, from iteration 10 of the first stage long enough to hold it
+    int64_t tune_at = -1;
+    if (o->autotune_rounds > 0 && !tuned &&
+        (n_it < 0 || n_it >= kTuneStart + loop_tuner::span(o->autotune_rounds))) {
+      tune_at = kTuneStart;
+      tuned = true;
+    }
     while ((n_it < 0 || k < n_it) && total < o->max_iters && !live.empty()) {
+      if (k == tune_at) {
+        rc = tuner_start(B, tuner, gamma, o->autotune_rounds);
+        if (rc != DL_OK) break;
+      }
       rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
       if (rc != DL_OK) break;
       rc = dl_launch_grad_batch(B->probs[live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream, B->glob);
@@ -555,8 +574,8 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
       ++k;
       ++total;
       for (int i : live) ++iters[i];
-      if (k == tune_at) {
-        rc = tune_batch(B, gamma, o->autotune_rounds);
+      if (tuner.running && --tuner.left == 0) {
+        rc = trial_end(B, tuner, gamma);
         if (rc != DL_OK) break;
       }
       if (last && o->check_every > 0 && k % o->check_every == 0) {
@@ -577,6 +596,7 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
           }
         }
         if (keep.size() != live.size()) {
+          tuner_abort(B, tuner);
           live = keep;
           if (!live.empty()) {
             rc = build_tables(B, live, gamma);

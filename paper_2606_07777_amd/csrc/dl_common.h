@@ -46,8 +46,15 @@ constexpr int DL_WAVES = DL_WG / 64;
 constexpr int DL_MAX_BUCKETS = 8;
 constexpr int DL_LONG = 7;               // bucket code of rows longer than 64*KMAX
 constexpr int DL_MAX_MJ = 13000;         // m*J that fits the LDS accumulation (12 B per entry)
+// Larger coupling blocks keep every dual row in LDS and split the histogram
+// rows into windows that fit beside them (the M_TILE mode): one launch per
+// window, each pass recomputing x and keeping the contributions to its rows.
+// Limits: DL_MAX_ITEMS items (16-bit item offsets) and LDS for the dual rows
+// plus, in the certificate's repair pass, one factor per item.
+constexpr int DL_MAX_ITEMS = 16383;
+constexpr size_t DL_LDS_BYTES = 160 * 1024;
 constexpr int DL_MAX_FAMILIES = 4;
-static_assert(4 * DL_MAX_MJ <= 0xFFFF, "item byte offsets 4 j are stored in 16 bits");
+static_assert(4 * DL_MAX_ITEMS <= 0xFFFF, "item byte offsets 4 j are stored in 16 bits");
 // Elements per lane in the group path: families with a == 1 only, and with a stored.
 #ifndef DL_KMAX_PLAIN
 #define DL_KMAX_PLAIN 12
@@ -92,6 +99,7 @@ enum : int {
   M_VIN = 8,     // v given in caller order (ProjectionMap), no gather
   M_XOUT = 16,   // write x in the caller's order
   M_GLOB = 32,   // with M_HIST: also count sum x for the global-count row
+  M_TILE = 64,   // with M_HIST: keep only the histogram rows of the launch's window (tile_b0, tile_bn)
 };
 
 struct dl_grad_args {
@@ -119,6 +127,7 @@ struct dl_grad_args {
   float neg_inv_gamma;
   float gamma;
   int32_t glob;                     // 1: a global-count row (dual mu[m*J], count into part[.. + m*J])
+  int32_t tile_b0, tile_bn;         // M_TILE: the window of histogram rows, in bytes (8 per row)
   const float* mu;                  // n_rows, lam in problem units (FP32)
   const float* rfac;                // J, repair factor (M_REPAIR)
   const float* v_in;                // nnz caller order (M_VIN)
@@ -146,6 +155,8 @@ struct dl_problem {
   double upper = 0.0;    // u of the box-cut set
   int32_t eq_mask = 0;   // bit k: family k holds equality rows (free duals)
   int32_t glob = 0;      // 1: one global-count row sum x <= gcap, dual coordinate m*J
+  int32_t tile_rows = 0;  // m*J > DL_MAX_MJ: histogram rows per window (M_TILE), else 0
+  int32_t n_tiles = 1;    // launches per histogram pass
   double gcap = 0.0;
   int64_t nrow() const { return (int64_t)m * J + glob; }
   int kmax = 16;
@@ -163,7 +174,7 @@ struct dl_problem {
 
   // reordered device layout
   int64_t* rp = nullptr;
-  uint16_t* idx = nullptr;   // item of every element as the byte offset 4 j (J <= DL_MAX_MJ < 16384)
+  uint16_t* idx = nullptr;   // item of every element as the byte offset 4 j (J <= DL_MAX_ITEMS)
   void* cval = nullptr;
   void* aval = nullptr;
   int64_t* orig_rp = nullptr;

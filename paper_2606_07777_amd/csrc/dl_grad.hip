@@ -28,6 +28,7 @@
 //    workgroup and summed over workgroups by the update kernel.
 #include <string.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "dl_common.h"
@@ -165,7 +166,7 @@ size_t dl_grad_lds_bytes(const dl_problem* P, int mode) {
   size_t mu_n = (mode & M_VIN) ? 0 : (size_t)P->nrow();
   size_t rf_n = (mode & M_REPAIR) ? (size_t)P->J : 0;
   size_t off = ((mu_n + rf_n) * 4 + 15) & ~(size_t)15;
-  size_t hist = (mode & M_HIST) ? mJ * 8 : 0;
+  size_t hist = (mode & M_HIST) ? (P->tile_rows > 0 ? (size_t)P->tile_rows : mJ) * 8 : 0;
   // per-wavefront objective sums, then per-wavefront global counts
   return off + hist + DL_WAVES * sizeof(double) + DL_WAVES * sizeof(unsigned long long);
 }
@@ -247,5 +248,18 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
   if (P->mf == 1 && !P->has_a)
     return bf ? dl_grad_launch_v_1_0_1(P, mode, A, lds) : dl_grad_launch_v_1_0_0(P, mode, A, lds);
   if (P->mf == 1) return bf ? dl_grad_launch_v_1_1_1(P, mode, A, lds) : dl_grad_launch_v_1_1_0(P, mode, A, lds);
-  return bf ? dl_grad_launch_v_4_1_1(P, mode, A, lds) : dl_grad_launch_v_4_1_0(P, mode, A, lds);
+  if (!(mode & M_HIST) || P->tile_rows == 0)
+    return bf ? dl_grad_launch_v_4_1_1(P, mode, A, lds) : dl_grad_launch_v_4_1_0(P, mode, A, lds);
+  // row windows: one launch each; the first also writes x, the objective and the
+  // global count (every launch computes the same x)
+  const int64_t mJ = (int64_t)P->m * P->J;
+  for (int t = 0; t < P->n_tiles; ++t) {
+    const int64_t r0 = (int64_t)t * P->tile_rows;
+    const int64_t n = std::min<int64_t>(P->tile_rows, mJ - r0);
+    A.tile_b0 = (int32_t)(8 * r0);
+    A.tile_bn = (int32_t)(8 * n);
+    const int mt = (t == 0) ? (mode | M_TILE) : ((mode & ~(M_OBJ | M_XOUT | M_GLOB)) | M_TILE);
+    DL_TRY(bf ? dl_grad_launch_v_4_1_1(P, mt, A, lds) : dl_grad_launch_v_4_1_0(P, mt, A, lds));
+  }
+  return DL_OK;
 }

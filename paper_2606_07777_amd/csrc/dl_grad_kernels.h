@@ -143,6 +143,19 @@ __device__ __forceinline__ void hist_add_pos(unsigned long long* h, int rb, floa
   if (q != 0) atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(h) + rb), (unsigned long long)q);
 }
 
+// One contribution to the histogram.  In the window mode only rows inside the
+// launch's window [tile_b0, tile_b0 + tile_bn) (bytes) are kept, at their offset
+// in the window.
+template <bool HAS_A, int MODE>
+__device__ __forceinline__ void hist_put(unsigned long long* h, int rb, float w, float qs, const dl_grad_args& A) {
+  if constexpr ((MODE & M_TILE) != 0) {
+    rb -= A.tile_b0;
+    if ((unsigned)rb >= (unsigned)A.tile_bn) return;
+  }
+  if constexpr (HAS_A) hist_add(h, rb, w, qs);
+  else hist_add_pos(h, rb, w, qs);
+}
+
 // Per-lane accumulators of one pass: the FP64 objective terms, and the
 // fixed-point count of the global-count row (sum x on the grid 1/qs_g).
 struct LaneAcc {
@@ -513,8 +526,7 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
             if constexpr (HAS_A) {
               if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
             }
-            if constexpr (HAS_A) hist_add(s_hist, f * 8 * A.J + 2 * item_off(R, k), w, qs[f]);
-            else hist_add_pos(s_hist, f * 8 * A.J + 2 * item_off(R, k), w, qs[f]);
+            hist_put<HAS_A, MODE>(s_hist, f * 8 * A.J + 2 * item_off(R, k), w, qs[f], A);
           }
         }
         // global-count row: x >= 0 on its own grid, summed per lane in 64 bits
@@ -758,8 +770,7 @@ __device__ __forceinline__ void long_task(const dl_grad_args& A, int64_t t, cons
       for (int f = 0; f < MF; ++f) {
         if (f < A.m) {
           float w = (HAS_A && A.a_slot[f] >= 0) ? af[HAS_A ? f : 0] * x : x;
-          if constexpr (HAS_A) hist_add(s_hist, f * 8 * A.J + 2 * j, w, qs[f]);
-          else hist_add_pos(s_hist, f * 8 * A.J + 2 * j, w, qs[f]);
+          hist_put<HAS_A, MODE>(s_hist, f * 8 * A.J + 2 * j, w, qs[f], A);
         }
       }
       if constexpr ((MODE & M_GLOB) != 0) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
@@ -786,8 +797,9 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
   float* s_rf = s_mu + mu_n;
   const int rf_n = (MODE & M_REPAIR) ? A.J : 0;
   size_t off = ((size_t)(mu_n + rf_n) * 4 + 15) & ~(size_t)15;
+  // the histogram: every item row, or (M_TILE) the rows of this launch's window
   unsigned long long* s_hist = reinterpret_cast<unsigned long long*>(smem + off);
-  const int hist_n = (MODE & M_HIST) ? mJ : 0;
+  const int hist_n = (MODE & M_HIST) ? (((MODE & M_TILE) != 0) ? (A.tile_bn >> 3) : mJ) : 0;
   double* s_obj = reinterpret_cast<double*>(smem + off + (size_t)hist_n * 8);
   unsigned long long* s_gc = reinterpret_cast<unsigned long long*>(s_obj + DL_WAVES);
 
@@ -852,7 +864,8 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
   __syncthreads();
   if (MODE & M_HIST) {
     unsigned long long* dst = A.part + (size_t)slot * nrow;
-    for (int r = tid; r < mJ; r += DL_WG) dst[r] = s_hist[r];
+    const int r0 = ((MODE & M_TILE) != 0) ? (A.tile_b0 >> 3) : 0;
+    for (int r = tid; r < hist_n; r += DL_WG) dst[r0 + r] = s_hist[r];
     if ((MODE & M_GLOB) && A.glob && tid == 0) {
       unsigned long long g_ = 0ull;
       for (int w = 0; w < DL_WAVES; ++w) g_ += s_gc[w];
@@ -906,6 +919,27 @@ dl_status launch_mode(const dl_problem* P, int mode, const dl_grad_args& A, size
     case M_HIST | M_XOUT | M_GLOB: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT | M_GLOB>(P, A, lds);
     case M_HIST | M_OBJ | M_XOUT | M_GLOB:
       return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB>(P, A, lds);
+    default: break;
+  }
+  // coupling blocks beyond one LDS histogram (row windows) run on the four-family kernel only
+  if constexpr (MF == 4) {
+    switch (mode) {
+      case M_HIST | M_TILE: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_TILE>(P, A, lds);
+      case M_HIST | M_OBJ | M_TILE: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_TILE>(P, A, lds);
+      case M_HIST | M_XOUT | M_TILE: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT | M_TILE>(P, A, lds);
+      case M_HIST | M_OBJ | M_XOUT | M_TILE:
+        return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_TILE>(P, A, lds);
+      case M_HIST | M_GLOB | M_TILE: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB | M_TILE>(P, A, lds);
+      case M_HIST | M_OBJ | M_GLOB | M_TILE:
+        return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_GLOB | M_TILE>(P, A, lds);
+      case M_HIST | M_XOUT | M_GLOB | M_TILE:
+        return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT | M_GLOB | M_TILE>(P, A, lds);
+      case M_HIST | M_OBJ | M_XOUT | M_GLOB | M_TILE:
+        return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB | M_TILE>(P, A, lds);
+      default: break;
+    }
+  }
+  switch (mode) {
     case M_REPAIR: return launch_one<MF, HAS_A, KMAX, TV, M_REPAIR>(P, A, lds);
     case M_VIN | M_XOUT: return launch_one<MF, HAS_A, KMAX, TV, M_VIN | M_XOUT>(P, A, lds);
     default: dl_set_error("internal: unknown gradient-pass mode"); return DL_EINVAL;
@@ -951,5 +985,17 @@ void set_attr_all() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if constexpr (MF == 4) {
+    const void* gk[] = {
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_TILE>,
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_TILE>,
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT | M_TILE>,
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_TILE>,
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB | M_TILE>,
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_GLOB | M_TILE>,
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_XOUT | M_GLOB | M_TILE>,
+        (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB | M_TILE>};
+    for (const void* k : gk) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  }
 }
 }  // namespace

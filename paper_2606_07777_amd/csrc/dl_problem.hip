@@ -266,8 +266,18 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   P->has_a = P->n_stored > 0;
 
   // degree buckets: 2^glog lanes per user, at most kmax elements per lane
-  P->mf = (m == 1) ? 1 : 4;
-  P->kmax = (m == 1 && !P->has_a) ? DL_KMAX_PLAIN : DL_KMAX_A;
+  // coupling blocks beyond one LDS histogram run the four-family kernel, one
+  // launch per window of histogram rows
+  if ((int64_t)m * J > DL_MAX_MJ) {
+    // histogram windows beside the dual rows in LDS, of equal size
+    const int64_t mJ = (int64_t)m * J;
+    const size_t mu_b = ((size_t)P->nrow() * 4 + 15) & ~(size_t)15;
+    const int64_t cap = (int64_t)((DL_LDS_BYTES - mu_b - 2 * DL_WAVES * 8) / 8);
+    P->n_tiles = (int32_t)((mJ + cap - 1) / cap);
+    P->tile_rows = (int32_t)((mJ + P->n_tiles - 1) / P->n_tiles);
+  }
+  P->mf = (m == 1 && P->tile_rows == 0) ? 1 : 4;
+  P->kmax = (P->mf == 1 && !P->has_a) ? DL_KMAX_PLAIN : DL_KMAX_A;
   const int kmax = P->kmax;
   DL_CHECK_ARG(d->layout == DL_LAYOUT_BUCKETED || d->layout == DL_LAYOUT_WAVEFRONT, "unknown layout");
   const bool wavefront = d->layout == DL_LAYOUT_WAVEFRONT;
@@ -546,8 +556,14 @@ extern "C" dl_status dl_problem_create(const dl_problem_desc* d, dl_problem** ou
   DL_CHECK_ARG(d->global_count == 0 || d->global_count == 1, "global_count must be 0 or 1");
   DL_CHECK_ARG(!d->global_count || (isfinite(d->global_cap) && d->global_cap >= 0.0),
                "global_cap must be finite and >= 0");
-  if (mJ > DL_MAX_MJ) {
-    dl_set_error("n_families * n_items exceeds the on-chip accumulation capacity (13000)");
+  if (d->n_items > DL_MAX_ITEMS) {
+    dl_set_error("n_items exceeds the 16-bit item offsets of this build (16383)");
+    return DL_EUNSUPPORTED;
+  }
+  // LDS of a workgroup: the dual rows and, in the repair pass, one factor per item
+  const int64_t rows = mJ + (d->global_count ? 1 : 0);
+  if ((size_t)(rows + d->n_items) * 4 + 512 > DL_LDS_BYTES) {
+    dl_set_error("n_rows + n_items exceeds what one workgroup stages in LDS (40,832 words)");
     return DL_EUNSUPPORTED;
   }
   dl_problem* P = new (std::nothrow) dl_problem();
@@ -640,6 +656,7 @@ extern "C" dl_status dl_problem_get_info(const dl_problem* P, dl_problem_info* o
   o->bytes_per_pass = (double)P->nnz * (2.0 + vb * (1 + P->n_stored)) + 8.0 * (double)(P->I + 1) +
                       (double)P->nrow() * 4.0;
   o->n_rows = P->nrow();
+  o->n_windows = P->n_tiles;
   o->device_bytes = P->device_bytes;
   o->max_degree = P->max_degree;
   o->n_buckets = (int32_t)P->buckets.size();

@@ -68,9 +68,12 @@ def test_unsupported_shapes_and_options(dl, base, wl):
         make(dl, dataclasses.replace(base, eq_families=0b100))        # family 2 does not exist
     with pytest.raises(RuntimeError):
         make(dl, dataclasses.replace(base, proj="boxcut", upper=0.0))  # box-cut needs u > 0
-    big = wl.random_small(91, 200, 14000, 5)                          # m J beyond the LDS accumulation
+    big = wl.random_small(91, 200, 16384, 5)                          # J beyond the 16-bit item offsets
     with pytest.raises(RuntimeError):
         make(dl, big)
+    wide = wl.random_small(92, 200, 14000, 5, n_families=2, a_ones=False)  # duals + factors beyond LDS
+    with pytest.raises(RuntimeError):
+        make(dl, wide)
 
 
 def test_bad_call_arguments(dl, base):

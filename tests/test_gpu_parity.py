@@ -630,10 +630,10 @@ def test_batch_matches_solo_solves(dl, orc, wl):
 
 
 def test_tuned_batch_matches_solo(dl, wl):
-    """The batch tuner re-deals workgroups between and inside members from measured
-    time after 50 iterations; every member still ends bitwise where its solo solve
-    ends, and the report describes the kept split.  A second solve on the same batch
-    without tuning starts again from the cost model."""
+    """The batch tuner re-deals workgroups between and inside members from the measured
+    time of the solve's own iterations (from iteration 10); every member still ends
+    bitwise where its solo solve ends, and the report describes the kept split.  A
+    second solve on the same batch without tuning starts again from the cost model."""
     members = [wl.batch_member(k, binding=True, scale=0.02) for k in range(6, 12)]
     sched = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[100, 100, -1], tol=1e-4, max_iters=3000, check_every=10)
     probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]

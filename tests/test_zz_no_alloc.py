@@ -55,3 +55,10 @@ def test_noalloc_rejects_what_it_cannot_hold(dl, wl):
     with pytest.raises(pkg.DualipError) as e:
         prob.solve([1e-2], [10], check_every=0, autotune_rounds=1, noalloc=True)
     assert "autotune" in str(e.value)
+    # 2 x 9,000 dual rows: a valid problem (the histogram in device memory) whose
+    # rows exceed the fixed state array
+    wide = dl.Problem.from_instance(wl.random_small(93, 2000, 9000, 8, n_families=2, a_ones=False), jacobi=True)
+    assert wide.nrow == 18_000
+    with pytest.raises(pkg.DualipError) as e:
+        wide.solve([1e-2], [10], check_every=0, noalloc=True)
+    assert e.value.status == -4 and "16384" in str(e.value)
