@@ -493,9 +493,10 @@ class Batch:
             pass
 
     def solve(self, gammas, iters, tol=1e-4, max_iters=20000, check_every=10, reset_momentum=True,
-              step_scale=1.0, lam0=None, autotune=0):
+              step_scale=1.0, lam0=None, autotune=2):
         """Returns ([lam tensor per member], [stats dict per member]).  autotune > 0
-        re-deals the workgroups from measured time that many rounds (see tune())."""
+        (the default) re-deals the workgroups from the measured time of the solve's own
+        iterations, that many rounds per grid (see tune()); 0 keeps the cost-model split."""
         torch = self.probs[0].torch
         n = len(self.probs)
         g = np.ascontiguousarray(gammas, dtype=np.float64)

@@ -1,5 +1,6 @@
-// Many independent instances solved together: one gradient-pass launch and one
-// update launch per iteration serve every live instance, whatever its size.
+// Many independent instances solved together: per iteration, one scale launch,
+// one gradient-pass launch, one slot-reduction launch and one update launch
+// serve every live instance, whatever its size.
 //
 // Workgroups are dealt to instances in proportion to their pass cost (several
 // per compute unit, so the hardware's workgroup dispatch evens out what the
@@ -29,6 +30,7 @@ namespace {
 
 struct bupd {
   const unsigned long long* part;
+  unsigned long long* acc;  // the member's reduced sums (its problem's accumulator, zero between passes)
   int n_slot;
   int mJ, J;        // item rows m*J, items J
   int nrow;         // dual rows: m*J, then the global-count row when present
@@ -49,8 +51,31 @@ struct bblk {
   int r0;
 };
 
+// A block of the slot reduction: slots [s0, s0 + DL_BRED_SLOTS) of member inst
+// for the 256 rows from r0.
+struct bred {
+  int inst;
+  int r0;
+  int s0;
+};
+constexpr int DL_BRED_SLOTS = 16;
+
+// Sums a block of a member's partial histograms into its accumulator (64-bit
+// integer atomics: exact in any order).  Short chains of loads per thread keep
+// the reduction parallel however many workgroups a member was dealt.
+__global__ void reduce_batch(const bupd* __restrict__ U, const bred* __restrict__ red) {
+  const bred R = red[blockIdx.x];
+  const bupd& u = U[R.inst];
+  const int r = R.r0 + (int)threadIdx.x;
+  if (r >= u.nrow) return;
+  const int s1 = min(u.n_slot, R.s0 + DL_BRED_SLOTS);
+  long long sum = 0;
+  for (int w = R.s0; w < s1; ++w) sum += (long long)u.part[(size_t)w * u.nrow + r];
+  if (sum != 0) atomicAdd(u.acc + r, (unsigned long long)sum);
+}
+
 // The fused accelerated step of every live instance (same arithmetic as the
-// single-instance update): reduce the partial slots in fixed order, step on the
+// single-instance update): take and clear the reduced sum, step on the
 // Jacobi-scaled dual, FISTA momentum, next gather point.
 __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict__ blk, double gamma,
                              double step_scale, double beta) {
@@ -58,8 +83,8 @@ __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict_
   const bupd& u = U[B.inst];
   const int r = B.r0 + (int)threadIdx.x;
   if (r >= u.nrow) return;
-  long long acc = 0;
-  for (int w = 0; w < u.n_slot; ++w) acc += (long long)u.part[(size_t)w * u.nrow + r];
+  const long long acc = (long long)u.acc[r];
+  u.acc[r] = 0ull;
   const int k = r < u.mJ ? r / u.J : DL_MAX_FAMILIES;  // the global-count row has its own scale
   const double ax = (double)acc / (double)u.qs[k];
   const double Dr = u.D[r];
@@ -90,9 +115,10 @@ struct dl_batch {
   dl_wg_desc* d_wgs = nullptr;
   bupd* d_upd = nullptr;
   bblk* d_blk = nullptr;
+  bred* d_red = nullptr;
   unsigned long long* d_part = nullptr;
   size_t part_cap = 0;
-  int n_wg = 0, n_blk = 0;
+  int n_wg = 0, n_blk = 0, n_red = 0;
   size_t lds = 0;
   bool glob = false;  // some live member has a global-count row
   // host mirrors
@@ -100,6 +126,7 @@ struct dl_batch {
   std::vector<dl_wg_desc> h_wgs;
   std::vector<bupd> h_upd;
   std::vector<bblk> h_blk;
+  std::vector<bred> h_red;
   std::vector<int> live;           // the instances the tables were built for
   std::vector<size_t> wg_first;    // per live position: its first workgroup in h_wgs
   // per-workgroup (start, end) clock stamps of a timed pass; clock_cap entries
@@ -114,7 +141,7 @@ struct dl_batch {
 static void free_batch(dl_batch* B) {
   if (!B) return;
   for (dl_solver* s : B->solvers) dl_solver_destroy(s);
-  void* ptrs[] = {B->d_args, B->d_wgs, B->d_upd, B->d_blk, B->d_part, B->d_clock};
+  void* ptrs[] = {B->d_args, B->d_wgs, B->d_upd, B->d_blk, B->d_red, B->d_part, B->d_clock};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete B;
@@ -171,6 +198,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
   B->h_wgs.clear();
   B->h_upd.clear();
   B->h_blk.clear();
+  B->h_red.clear();
   size_t part_need = 0, lds = 0;
   std::vector<size_t> part_off(live.size(), 0);
   for (size_t q = 0; q < live.size(); ++q) {
@@ -214,6 +242,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     bupd u;
     memset(&u, 0, sizeof(u));
     u.part = A.part;
+    u.acc = P->acc;
     u.n_slot = w[q];
     u.mJ = P->m * P->J;
     u.nrow = (int)P->nrow();
@@ -230,22 +259,29 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     u.lhat = P->lhat;
     const int ui = (int)B->h_upd.size();
     B->h_upd.push_back(u);
-    for (int r0 = 0; r0 < u.nrow; r0 += 256) B->h_blk.push_back({ui, r0});
+    for (int r0 = 0; r0 < u.nrow; r0 += 256) {
+      B->h_blk.push_back({ui, r0});
+      for (int s0 = 0; s0 < u.n_slot; s0 += DL_BRED_SLOTS) B->h_red.push_back({ui, r0, s0});
+    }
   }
   B->n_wg = (int)B->h_wgs.size();
   B->n_blk = (int)B->h_blk.size();
+  B->n_red = (int)B->h_red.size();
   B->lds = lds;
   B->glob = false;
   for (int i : live) B->glob = B->glob || B->probs[i]->glob;
   if (B->d_wgs) DL_HIP_TRY(hipFree(B->d_wgs));
   if (B->d_upd) DL_HIP_TRY(hipFree(B->d_upd));
   if (B->d_blk) DL_HIP_TRY(hipFree(B->d_blk));
+  if (B->d_red) DL_HIP_TRY(hipFree(B->d_red));
   B->d_wgs = nullptr;
   B->d_upd = nullptr;
   B->d_blk = nullptr;
+  B->d_red = nullptr;
   DL_HIP_TRY(hipMalloc((void**)&B->d_wgs, sizeof(dl_wg_desc) * std::max<size_t>(1, B->h_wgs.size())));
   DL_HIP_TRY(hipMalloc((void**)&B->d_upd, sizeof(bupd) * std::max<size_t>(1, B->h_upd.size())));
   DL_HIP_TRY(hipMalloc((void**)&B->d_blk, sizeof(bblk) * std::max<size_t>(1, B->h_blk.size())));
+  DL_HIP_TRY(hipMalloc((void**)&B->d_red, sizeof(bred) * std::max<size_t>(1, B->h_red.size())));
   hipStream_t st = B->stream;
   DL_HIP_TRY(hipMemcpyAsync(B->d_args, B->h_args.data(), sizeof(dl_grad_args) * B->n, hipMemcpyHostToDevice, st));
   if (!B->h_wgs.empty())
@@ -255,6 +291,8 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     DL_HIP_TRY(hipMemcpyAsync(B->d_upd, B->h_upd.data(), sizeof(bupd) * B->h_upd.size(), hipMemcpyHostToDevice, st));
   if (!B->h_blk.empty())
     DL_HIP_TRY(hipMemcpyAsync(B->d_blk, B->h_blk.data(), sizeof(bblk) * B->h_blk.size(), hipMemcpyHostToDevice, st));
+  if (!B->h_red.empty())
+    DL_HIP_TRY(hipMemcpyAsync(B->d_red, B->h_red.data(), sizeof(bred) * B->h_red.size(), hipMemcpyHostToDevice, st));
   DL_HIP_TRY(hipStreamSynchronize(st));  // host tables must outlive the copies
   return DL_OK;
 }
@@ -521,6 +559,15 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
       return cs;
     }
   }
+  // every member's accumulator starts at zero (each reader of a reduction clears it)
+  for (int i = 0; i < B->n; ++i)
+    if (hipMemsetAsync(B->probs[i]->acc, 0, sizeof(unsigned long long) * (size_t)B->probs[i]->nrow(), B->stream) !=
+        hipSuccess) {
+      for (dl_solver* s : B->solvers) dl_solver_destroy(s);
+      B->solvers.clear();
+      dl_set_error("hipMemsetAsync failed");
+      return DL_EHIP;
+    }
   std::vector<int> live(B->n);
   std::iota(live.begin(), live.end(), 0);
   std::vector<char> done(B->n, 0);
@@ -564,6 +611,8 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
       const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
       const double beta = (tk - 1.0) / tn;
       tk = tn;
+      if (B->n_red > 0)
+        hipLaunchKernelGGL(reduce_batch, dim3(B->n_red), dim3(256), 0, B->stream, B->d_upd, B->d_red);
       hipLaunchKernelGGL(update_batch, dim3(B->n_blk), dim3(256), 0, B->stream, B->d_upd, B->d_blk, gamma,
                          step_scale, beta);
       if (hipGetLastError() != hipSuccess) {

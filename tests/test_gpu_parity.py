@@ -649,7 +649,7 @@ def test_tuned_batch_matches_solo(dl, wl):
         print(f"member {k}: I={m.n_users} nnz={m.nnz} iters batch {st_b[k]['iters']} solo {st_s['iters']}")
         assert st_b[k]["iters"] == st_s["iters"]
         assert np.array_equal(lam_b[k].cpu().numpy(), lam_s.cpu().numpy())
-    lam_u, st_u = batch.solve(**sched)
+    lam_u, st_u = batch.solve(autotune=0, **sched)
     assert batch.tune()["rounds"] == 0
     for k in range(len(members)):
         assert np.array_equal(lam_u[k].cpu().numpy(), lam_b[k].cpu().numpy())
