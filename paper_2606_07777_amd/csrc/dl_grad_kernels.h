@@ -259,12 +259,31 @@ __device__ __forceinline__ void ld4<float>(const float* p, float* out) {
 }
 template <>
 __device__ __forceinline__ void ld4<uint16_t>(const uint16_t* p, float* out) {
-  // four BF16 values, little-endian pairs
+  // four BF16 values as two packed words, parked in the chunk's upper two
+  // registers; unpack_rows spreads them where they are first used (unpacking
+  // here would make the wavefront wait for the loads of the task it prefetches)
   const dl_v2u v = *reinterpret_cast<const dl_v2u*>(p);
-  out[0] = __uint_as_float(v.x << 16);
-  out[1] = __uint_as_float(v.x & 0xFFFF0000u);
-  out[2] = __uint_as_float(v.y << 16);
-  out[3] = __uint_as_float(v.y & 0xFFFF0000u);
+  out[2] = __uint_as_float(v.x);
+  out[3] = __uint_as_float(v.y);
+}
+
+// The chunks of a row that ld4 loaded as packed BF16 words, as FP32 values
+// (bit moves only).  Nothing to do for FP32 rows.
+template <typename TV, int KMAX>
+__device__ __forceinline__ void unpack_rows(float (&x)[KMAX], int K) {
+  if constexpr (sizeof(TV) == 2) {
+#pragma unroll
+    for (int k4 = 0; k4 < KMAX / 4; ++k4) {
+      if (4 * k4 < K) {
+        const uint32_t w0 = __float_as_uint(x[4 * k4 + 2]);
+        const uint32_t w1 = __float_as_uint(x[4 * k4 + 3]);
+        x[4 * k4 + 0] = __uint_as_float(w0 << 16);
+        x[4 * k4 + 1] = __uint_as_float(w0 & 0xFFFF0000u);
+        x[4 * k4 + 2] = __uint_as_float(w1 << 16);
+        x[4 * k4 + 3] = __uint_as_float(w1 & 0xFFFF0000u);
+      }
+    }
+  }
 }
 
 // Issues the loads of one task's rows (slot k of lane lid: see slot_off).
@@ -320,6 +339,14 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
   const unsigned d = (unsigned)(m.e - m.s);
   const int lo = row_shift(m) - slot_off<GLOG>(0, lid);
   const int mm = A.m;
+  if constexpr ((MODE & M_VIN) == 0) {
+    unpack_rows<TV, KMAX>(R.c, K);
+    if constexpr (HAS_A) {
+#pragma unroll
+      for (int f = 0; f < MF; ++f)
+        if (f < mm && A.a_slot[f] >= 0) unpack_rows<TV, KMAX>(R.a[f], K);
+    }
+  }
   // the global-count row's dual: folded into the staged family-0 words when
   // family 0 has a == 1, added here when its a is stored
   float mug = 0.f;
