@@ -61,10 +61,12 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(args):
-    """HBM bytes per gradient pass from the committed rocprofv3 counter summary, when it
-    was taken on the current kernel source and this workload; otherwise None."""
-    path = os.path.join(ROOT, "profiles", "grad_pass_production_traffic.json")
-    if not os.path.exists(path) or args.workload != "production" or args.storage != "f32" or args.layout != "bucketed":
+    """HBM bytes per gradient pass from the committed rocprofv3 counter summary of this
+    storage form, when it was taken on the current kernel source and the production
+    workload; otherwise None."""
+    name = "grad_pass_production_traffic.json" if args.storage == "f32" else "grad_pass_production_bf16_traffic.json"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path) or args.workload != "production" or args.layout != "bucketed":
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha1") != kernel_source_hash():

@@ -25,6 +25,8 @@
 
 struct dl_solver;  // dl_solver.hip
 dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag);
+dl_status dl_solver_certificate_enqueue(dl_solver* S);
+dl_status dl_solver_certificate_read(dl_solver* S, dl_solve_stats* out);
 
 namespace {
 
@@ -628,9 +630,21 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
         if (rc != DL_OK) break;
       }
       if (last && o->check_every > 0 && k % o->check_every == 0) {
+        // every live member's certificate on the stream, one synchronisation
+        std::vector<dl_status> enq(B->n, DL_OK);
+        for (int i : live) enq[i] = dl_solver_certificate_enqueue(B->solvers[i]);
+        if (hipStreamSynchronize(B->stream) != hipSuccess) {
+          dl_set_error("hipStreamSynchronize failed");
+          rc = DL_EHIP;
+          break;
+        }
         std::vector<int> keep;
         for (int i : live) {
-          dl_status cs = dl_solver_certificate(B->solvers[i], &stats[i]);
+          dl_status cs = enq[i] != DL_OK ? enq[i] : dl_solver_certificate_read(B->solvers[i], &stats[i]);
+          if (enq[i] != DL_OK) {
+            memset(&stats[i], 0, sizeof(stats[i]));
+            stats[i].status = enq[i];
+          }
           ++checks[i];
           if (cs != DL_OK) {
             stats[i].status = cs;

@@ -206,7 +206,7 @@ struct dl_problem {
   double* lam_tmp = nullptr;           // n_rows
   double* cert_out = nullptr;          // 8 doubles
   int* upd_flag = nullptr;             // dl_problem_update's non-finite flag
-  double* cert_host = nullptr;         // pinned, 8 doubles
+  double* cert_host = nullptr;         // pinned, 16 doubles: certificate values [0..3], its flag word at [8]
   double device_bytes = 0;
 };
 

@@ -261,7 +261,11 @@ dl_status next_event_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, siz
 }
 
 // Certificate at the solver's current lam (Table 4 metrics, certified gap).
-dl_status certificate(dl_solver* S, dl_solve_stats* st) {
+// Enqueues the certificate at the solver's lam on the problem's stream; its
+// values and the non-finite flag land in the problem's pinned host words
+// (cert_host[0..3], and the flag as an int at cert_host + 8) once the stream
+// has passed them.
+dl_status certificate_enqueue(dl_solver* S) {
   dl_problem* P = S->P;
   const int mJ = (int)P->nrow();  // dual rows
   DL_TRY(dl_launch_grad(P, M_HIST | M_OBJ, S->mu_lam, S->gamma, nullptr, nullptr, nullptr, P->obj_part));
@@ -277,9 +281,16 @@ dl_status certificate(dl_solver* S, dl_solve_stats* st) {
   hipLaunchKernelGGL(cert_final, dim3(1), dim3(1024), 0, P->stream, P->pobj_part, P->n_wg, P->cert_out);
   DL_HIP_TRY(hipGetLastError());
   DL_HIP_TRY(hipMemcpyAsync(P->cert_host, P->cert_out, sizeof(double) * 4, hipMemcpyDeviceToHost, P->stream));
-  int hflag = 0;
-  DL_HIP_TRY(hipMemcpyAsync(&hflag, S->flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
-  DL_HIP_TRY(hipStreamSynchronize(P->stream));
+  DL_HIP_TRY(hipMemcpyAsync(reinterpret_cast<int*>(P->cert_host + 8), S->flag, sizeof(int), hipMemcpyDeviceToHost,
+                            P->stream));
+  return DL_OK;
+}
+
+// The statistics of a certificate enqueued earlier; the caller has
+// synchronised the stream past it.
+dl_status certificate_read(dl_solver* S, dl_solve_stats* st) {
+  dl_problem* P = S->P;
+  const int hflag = *reinterpret_cast<const int*>(P->cert_host + 8);
   const double g = P->cert_host[0], pobj = P->cert_host[3];
   st->gamma = S->gamma;
   st->dual_obj = g;
@@ -300,7 +311,23 @@ dl_status certificate(dl_solver* S, dl_solve_stats* st) {
   return DL_OK;
 }
 
+dl_status certificate(dl_solver* S, dl_solve_stats* st) {
+  DL_TRY(certificate_enqueue(S));
+  DL_HIP_TRY(hipStreamSynchronize(S->P->stream));
+  return certificate_read(S, st);
+}
+
 }  // namespace
+
+// Split certificate for callers that check many solvers on one stream: enqueue
+// each, synchronise once, then read each.
+dl_status dl_solver_certificate_enqueue(dl_solver* S) { return certificate_enqueue(S); }
+dl_status dl_solver_certificate_read(dl_solver* S, dl_solve_stats* out) {
+  memset(out, 0, sizeof(*out));
+  const dl_status s = certificate_read(S, out);
+  out->status = s;
+  return s;
+}
 
 // ---------------------------------------------------------------------------
 // ObjectiveFunction and ProjectionMap
