@@ -297,10 +297,10 @@ def learned_eval(args, log=log):
             "days": days}
 
 
-def member_rates(members, probs):
-    """Solo gradient-pass time of every batch member (HIP events around 30 passes at
-    gamma 0.1 after 30 untimed iterations) against one batched pass.  Prints its own
-    JSON line."""
+def member_rates(members, probs, gamma=1e-1, warm=30):
+    """Solo gradient-pass time of every batch member (HIP events around 30 passes,
+    after `warm` untimed iterations at gamma 0.1 and, when gamma differs, 5 more at
+    gamma) against one batched iteration.  Prints its own JSON line."""
     import torch
 
     import paper_2606_07777_amd as dl
@@ -308,7 +308,10 @@ def member_rates(members, probs):
     for m, p in zip(members, probs):
         s = p.solver()
         s.set_stage(1e-1)
-        s.step(30)
+        s.step(warm)
+        if gamma != 1e-1:
+            s.set_stage(gamma)
+            s.step(5)
         s.enable_timing(True)
         s.step(30)
         t = s.timing()
@@ -330,7 +333,7 @@ def member_rates(members, probs):
            "solo_GBps_min": min(r["GBps"] for r in rows), "solo_GBps_max": max(r["GBps"] for r in rows),
            "batched_GBps": sum(r["bytes_per_pass"] for r in rows) / (tr["pass_ms_tuned"] * 1e-3) / 1e9,
            "members": rows,
-           "config": {"workload": f"uneven batch of {len(members)}"}}
+           "config": {"workload": f"uneven batch of {len(members)}", "gamma": gamma, "warm_iterations": warm}}
     print(json.dumps(out), flush=True)
 
 
@@ -355,7 +358,7 @@ def batch_bench(args):
     torch.cuda.set_device(0)
     probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]
     if args.member_rates:
-        return member_rates(members, probs)
+        return member_rates(members, probs, args.rates_gamma, args.rates_warmup)
     sched = dict(gammas=[1e-1, 1e-2, 1e-3], iters=[300, 300, -1], tol=1e-4, max_iters=20000, check_every=10)
     batch = dl.Batch(probs)
     # untimed warm-up (first launches of every kernel)
@@ -445,6 +448,10 @@ def main():
                     help="with --workload batch: per-member solo pass rates against one batched pass")
     ap.add_argument("--no-batch-solo", action="store_true",
                     help="batch workload: time the batched solves only (no sequential solo solves)")
+    ap.add_argument("--rates-gamma", type=float, default=1e-1, help="--member-rates: gamma of the timed passes")
+    ap.add_argument("--rates-warmup", type=int, default=30, help="--member-rates: untimed iterations at gamma 0.1 first")
+    ap.add_argument("--timed-gamma", type=float, default=1e-2,
+                    help="gamma of the timed steps (after --warmup iterations at 0.1; 5 more at this gamma if it differs)")
     ap.add_argument("--batch-tune", type=int, default=2,
                     help="balancing rounds of the batch tuner (0: cost-model split only)")
     ap.add_argument("--users", type=int, default=10_000_000)
@@ -507,8 +514,9 @@ def main():
     # warm-up: the first continuation stage, so the timed steps see a realistic active set
     s.set_stage(1e-1, 1.0, True)
     s.step(args.warmup)
-    s.set_stage(1e-2, 1.0, True)
-    s.step(5)
+    if args.timed_gamma != 1e-1:
+        s.set_stage(args.timed_gamma, 1.0, True)
+        s.step(5)
     tune = None
     if args.tune_rounds > 0:
         tune = s.autotune(args.tune_rounds)
@@ -532,7 +540,7 @@ def main():
     value = inst.nnz * args.steps / el
     cert = s.certificate()
     log(f"{args.steps} steps: {ms_step:.3f} ms/step, grad pass {grad_ms:.3f} ms ({achieved:.0f} GB/s), "
-        f"update {upd_ms:.3f} ms; gap at gamma=1e-2 after warm-up: {cert['rel_gap']:.3e}")
+        f"update {upd_ms:.3f} ms; gap at gamma={args.timed_gamma:g} after warm-up: {cert['rel_gap']:.3e}")
     # the practical read ceiling: a streaming read of as many bytes as one pass reads
     ceiling = dl.read_bandwidth(int(bytes_pass), reps=20)
     torch.cuda.empty_cache()
@@ -552,7 +560,7 @@ def main():
         "dtype": "f32" if args.storage == "f32" else "bf16-storage/f32",
         "data": "synthetic",
         "config": {"workload": desc, "n_users": inst.n_users, "n_items": inst.n_items, "nnz": inst.nnz,
-                   "storage": args.storage, "layout": args.layout, "gamma_timed": 1e-2,
+                   "storage": args.storage, "layout": args.layout, "gamma_timed": args.timed_gamma,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args),

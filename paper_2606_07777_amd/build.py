@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libdualip.so")
 SOURCES = ["dl_problem.hip", "dl_grad.hip", "dl_solver.hip", "dl_batch.hip", "dl_mlp.hip", "dl_measure.hip"]
 # The gradient-pass kernels are compiled once per variant (families class,
 # stored a, BF16 storage), each build its own object, so they compile in parallel.
-GRAD_VARIANTS = [(1, 0, 0), (1, 0, 1), (1, 1, 0), (1, 1, 1), (4, 1, 0), (4, 1, 1)]
+GRAD_VARIANTS = [(1, 0, 0), (1, 0, 1), (1, 1, 0), (1, 1, 1), (2, 1, 0), (2, 1, 1), (4, 1, 0), (4, 1, 1)]
 # The gradient pass never forms a NaN (its inputs are checked finite and its
 # padding lanes are kept at -inf / 0), so its float min / max need no NaN
 # quieting; the other sources keep IEEE NaN semantics (their divergence checks

@@ -160,7 +160,7 @@ struct dl_problem {
   double gcap = 0.0;
   int64_t nrow() const { return (int64_t)m * J + glob; }
   int kmax = 16;
-  int mf = 1;            // compiled family bound of the kernel variant (1 or 4)
+  int mf = 1;            // compiled family bound of the kernel variant (1, 2 or 4)
   bool has_a = false;    // at least one stored family
   int n_stored = 0;
   int a_slot[DL_MAX_FAMILIES] = {-1, -1, -1, -1};

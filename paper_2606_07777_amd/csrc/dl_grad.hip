@@ -43,6 +43,8 @@ DL_GV_DECL(1, 0, 0)
 DL_GV_DECL(1, 0, 1)
 DL_GV_DECL(1, 1, 0)
 DL_GV_DECL(1, 1, 1)
+DL_GV_DECL(2, 1, 0)
+DL_GV_DECL(2, 1, 1)
 DL_GV_DECL(4, 1, 0)
 DL_GV_DECL(4, 1, 1)
 #undef DL_GV_DECL
@@ -178,6 +180,9 @@ dl_status dl_grad_prepare(const dl_problem* P) {
   } else if (P->mf == 1) {
     dl_grad_attr_v_1_1_0();
     dl_grad_attr_v_1_1_1();
+  } else if (P->mf == 2) {
+    dl_grad_attr_v_2_1_0();
+    dl_grad_attr_v_2_1_1();
   } else {
     dl_grad_attr_v_4_1_0();
     dl_grad_attr_v_4_1_1();
@@ -195,6 +200,9 @@ dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args
   if (P->mf == 1)
     return bf ? dl_grad_batch_v_1_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
               : dl_grad_batch_v_1_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
+  if (P->mf == 2)
+    return bf ? dl_grad_batch_v_2_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
+              : dl_grad_batch_v_2_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
   return bf ? dl_grad_batch_v_4_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
             : dl_grad_batch_v_4_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
 }
@@ -248,8 +256,11 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
   if (P->mf == 1 && !P->has_a)
     return bf ? dl_grad_launch_v_1_0_1(P, mode, A, lds) : dl_grad_launch_v_1_0_0(P, mode, A, lds);
   if (P->mf == 1) return bf ? dl_grad_launch_v_1_1_1(P, mode, A, lds) : dl_grad_launch_v_1_1_0(P, mode, A, lds);
-  if (!(mode & M_HIST) || P->tile_rows == 0)
-    return bf ? dl_grad_launch_v_4_1_1(P, mode, A, lds) : dl_grad_launch_v_4_1_0(P, mode, A, lds);
+  auto launch_multi = [&](int md) -> dl_status {
+    if (P->mf == 2) return bf ? dl_grad_launch_v_2_1_1(P, md, A, lds) : dl_grad_launch_v_2_1_0(P, md, A, lds);
+    return bf ? dl_grad_launch_v_4_1_1(P, md, A, lds) : dl_grad_launch_v_4_1_0(P, md, A, lds);
+  };
+  if (!(mode & M_HIST) || P->tile_rows == 0) return launch_multi(mode);
   // row windows: one launch each; the first also writes x, the objective and the
   // global count (every launch computes the same x)
   const int64_t mJ = (int64_t)P->m * P->J;
@@ -259,7 +270,7 @@ dl_status dl_launch_grad(const dl_problem* P, int mode, const float* mu, double 
     A.tile_b0 = (int32_t)(8 * r0);
     A.tile_bn = (int32_t)(8 * n);
     const int mt = (t == 0) ? (mode | M_TILE) : ((mode & ~(M_OBJ | M_XOUT | M_GLOB)) | M_TILE);
-    DL_TRY(bf ? dl_grad_launch_v_4_1_1(P, mt, A, lds) : dl_grad_launch_v_4_1_0(P, mt, A, lds));
+    DL_TRY(launch_multi(mt));
   }
   return DL_OK;
 }

@@ -596,7 +596,9 @@ __device__ __forceinline__ void run_bucket(const dl_grad_args& A, const dl_bucke
   // keeps per-bucket lane arithmetic inside this bucket's code (otherwise it is
   // hoisted out of the kernel's bucket loop for every bucket at once and spills)
   asm volatile("" : "+v"(lane));
-  constexpr bool PF = (MF == 1) && !(MODE & M_REPAIR);
+  // software pipelining needs two tasks' rows in registers: with four families'
+  // coefficients that spills within the 128 registers of 16 waves per CU
+  constexpr bool PF = (MF <= 2) && !(MODE & M_REPAIR);
   constexpr int G = 1 << GLOG;
   const int lid = lane & (G - 1);
   constexpr bool need_os = (MODE & (M_VIN | M_XOUT)) != 0;
@@ -948,8 +950,8 @@ dl_status launch_mode(const dl_problem* P, int mode, const dl_grad_args& A, size
       return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB>(P, A, lds);
     default: break;
   }
-  // coupling blocks beyond one LDS histogram (row windows) run on the four-family kernel only
-  if constexpr (MF == 4) {
+  // coupling blocks beyond one LDS histogram (row windows) run on the multi-family kernels only
+  if constexpr (MF >= 2) {
     switch (mode) {
       case M_HIST | M_TILE: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_TILE>(P, A, lds);
       case M_HIST | M_OBJ | M_TILE: return launch_one<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_TILE>(P, A, lds);
@@ -1012,7 +1014,7 @@ void set_attr_all() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT | M_GLOB>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  if constexpr (MF == 4) {
+  if constexpr (MF >= 2) {
     const void* gk[] = {
         (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_TILE>,
         (const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_TILE>,

@@ -1,5 +1,5 @@
 // One kernel variant of the gradient pass: this file is compiled once per
-// (family class, stored a, storage type), chosen by DL_GV_MF (1 or 4),
+// (family class, stored a, storage type), chosen by DL_GV_MF (1, 2 or 4),
 // DL_GV_A (0: every a == 1, 1: some family stored) and DL_GV_BF16 (0: FP32
 // values, 1: BF16), so the variants build in parallel.  Each build exports
 // the three entry points that dl_grad.hip dispatches to.

@@ -266,7 +266,7 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   P->has_a = P->n_stored > 0;
 
   // degree buckets: 2^glog lanes per user, at most kmax elements per lane
-  // coupling blocks beyond one LDS histogram run the four-family kernel, one
+  // coupling blocks beyond one LDS histogram run a multi-family kernel, one
   // launch per window of histogram rows
   if ((int64_t)m * J > DL_MAX_MJ) {
     // histogram windows beside the dual rows in LDS, of equal size
@@ -276,7 +276,8 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
     P->n_tiles = (int32_t)((mJ + cap - 1) / cap);
     P->tile_rows = (int32_t)((mJ + P->n_tiles - 1) / P->n_tiles);
   }
-  P->mf = (m == 1 && P->tile_rows == 0) ? 1 : 4;
+  // kernel variant by family count: one family (unless windowed), two, or up to four
+  P->mf = (m == 1 && P->tile_rows == 0) ? 1 : (m <= 2 ? 2 : 4);
   P->kmax = (P->mf == 1 && !P->has_a) ? DL_KMAX_PLAIN : DL_KMAX_A;
   const int kmax = P->kmax;
   DL_CHECK_ARG(d->layout == DL_LAYOUT_BUCKETED || d->layout == DL_LAYOUT_WAVEFRONT, "unknown layout");

@@ -32,7 +32,9 @@ def _cases(wl):
     one = wl.tiny_plain(seed=6, binding=True, n_users=150_000, n_items=14_000, mean_degree=12.0)
     return {"two_family_10k": (two, 2e-2), "one_family_14k": (one, 1e-2),
             "two_family_10k_global": (dataclasses.replace(two, global_cap=0.2 * two.nnz), 2e-2),
-            "two_family_10k_bf16": (two, 2e-2)}
+            "two_family_10k_bf16": (two, 2e-2),
+            # three stored families of 5,000 items: the four-family kernel in two windows
+            "three_family_5k": (wl.random_small(9, 40_000, 5000, 30, n_families=3, a_ones=False, proj="box"), 2e-2)}
 
 
 def _lam_point(orc, inst, gamma, seed):
@@ -42,7 +44,7 @@ def _lam_point(orc, inst, gamma, seed):
 
 
 @pytest.mark.parametrize("name", ["two_family_10k", "one_family_14k", "two_family_10k_global",
-                                  "two_family_10k_bf16"])
+                                  "two_family_10k_bf16", "three_family_5k"])
 def test_large_block_dual_grad_matches_oracle(dl, orc, wl, name):
     """BF16 storage: the oracle runs on the instance with c and a rounded to BF16,
     which is the data the GPU computes with."""

@@ -40,11 +40,15 @@ def _cases(wl):
         "boxcut": (wl.random_small(55, 6000, 400, 300, proj="boxcut", radius=1.0, upper=0.3, b_scale=0.2), 1e-2),
         "boxcut_long_rows": (wl.random_small(56, 3000, 3500, 3000, proj="boxcut", radius=2.0, upper=0.25,
                                              b_scale=0.2), 5e-2),
+        # the four-family kernel: three stored families, and four with family 0 at a == 1
+        "three_family_box": (wl.random_small(58, 4000, 200, 100, n_families=3, a_ones=False, proj="box"), 2e-2),
+        "four_family_simplex": (wl.random_small(59, 4000, 150, 80, n_families=4, a_ones=True, b_scale=0.02), 1e-2),
     }
 
 
 CASE_NAMES = ["tiny_plain_binding", "all_buckets_long_rows", "two_family_box", "simplex_eq", "explicit_a",
-              "production_small", "appendix_a", "boxcut", "boxcut_long_rows"]
+              "production_small", "appendix_a", "boxcut", "boxcut_long_rows", "three_family_box",
+              "four_family_simplex"]
 
 
 @pytest.fixture(scope="module")
@@ -151,7 +155,7 @@ def test_dual_grad_matches_oracle(dl, orc, cases, name, layout):
 
 
 @pytest.mark.parametrize("name", ["tiny_plain_binding", "all_buckets_long_rows", "simplex_eq", "two_family_box",
-                                  "boxcut", "boxcut_long_rows"])
+                                  "boxcut", "boxcut_long_rows", "four_family_simplex"])
 def test_project_matches_oracle(dl, orc, cases, name):
     import torch
     inst, _ = cases[name]
@@ -165,7 +169,8 @@ def test_project_matches_oracle(dl, orc, cases, name):
     assert np.all(np.abs(x - xo) <= tol), np.abs(x - xo).max()
 
 
-@pytest.mark.parametrize("name", ["tiny_plain_binding", "two_family_box", "boxcut", "all_buckets_long_rows"])
+@pytest.mark.parametrize("name", ["tiny_plain_binding", "two_family_box", "boxcut", "all_buckets_long_rows",
+                                  "three_family_box"])
 def test_certificate_matches_oracle(dl, orc, cases, name):
     """The certificate (dual value, repaired primal value, relative gap, max slack,
     Lagrangian gap) at a fixed point lam, against the oracle's at the same FP32
@@ -345,6 +350,19 @@ def test_continuation_solve_matches_oracle(dl, orc, wl):
     _cert_close(st, so, inst, prob, lo.astype(np.float32).astype(np.float64), 1e-3)
 
 
+@pytest.mark.parametrize("name", ["two_family_box", "three_family_box", "four_family_simplex"])
+def test_multi_family_trajectory(dl, orc, cases, name):
+    """gamma 0.1 -> 0.01, 150 iterations each, Jacobi: the two-family kernel (two
+    tasks' rows in flight per wavefront) and the four-family kernel against the oracle."""
+    inst, _ = cases[name]
+    prob = dl.Problem.from_instance(inst, jacobi=True)
+    sched = dict(gammas=[1e-1, 1e-2], iters=[150, 150])
+    lam, _ = prob.solve(**sched, check_every=0)
+    lo, _, _, _ = orc.solve(inst, sched["gammas"], sched["iters"], jacobi=True, check_every=0)
+    assert np.linalg.norm(lo) > 0
+    _lam_close(lam.cpu().numpy(), lo, what=f"{name} trajectory")
+
+
 @pytest.mark.parametrize("gamma", [10.0, 1e3])
 def test_dual_objective_at_large_gamma(dl, orc, cases, gamma):
     """Regression: the objective terms of padding lanes (v = -inf) must not be
@@ -447,11 +465,11 @@ def test_halving_continuation_matches_oracle(dl, orc, wl):
         _lam_close(lam.cpu().numpy(), lo, what=f"halving, jacobi {jac}")
 
 
-@pytest.mark.parametrize("variant", ["two_family_bf16", "stored_a_f32", "boxcut_equality"])
+@pytest.mark.parametrize("variant", ["two_family_bf16", "stored_a_f32", "boxcut_equality", "four_family"])
 def test_batch_kernel_variants_match_solo(dl, wl, variant):
-    """The batched kernels of the other variants (four-family kernel with BF16,
-    one stored family, box-cut with an equality family): every member ends
-    bitwise where its solo run ends."""
+    """The batched kernels of the other variants (two-family kernel with BF16,
+    one stored family, box-cut with an equality family, the four-family kernel):
+    every member ends bitwise where its solo run ends."""
     import dataclasses
     if variant == "two_family_bf16":
         members = [wl.random_small(300 + k, 3000 + 700 * k, 120, 40, n_families=2, a_ones=False, proj="box")
@@ -459,6 +477,10 @@ def test_batch_kernel_variants_match_solo(dl, wl, variant):
         kw = dict(storage="bf16")
     elif variant == "stored_a_f32":
         members = [wl.random_small(310 + k, 2500 + 900 * k, 150, 60, a_ones=False) for k in range(3)]
+        kw = {}
+    elif variant == "four_family":
+        members = [wl.random_small(330 + k, 2500 + 600 * k, 90, 40, n_families=4, a_ones=True, proj="box")
+                   for k in range(3)]
         kw = {}
     else:
         members = []
@@ -559,7 +581,7 @@ def _rounded(orc, inst):
                               inst.item_idx, orc.bf16_round(inst.c), a, inst.b, inst.proj, inst.radius)
 
 
-@pytest.mark.parametrize("name", ["two_family_box", "production_small", "explicit_a"])
+@pytest.mark.parametrize("name", ["two_family_box", "production_small", "explicit_a", "three_family_box"])
 def test_bf16_dual_grad_matches_oracle_on_rounded_data(dl, orc, cases, name):
     """With BF16 storage the GPU computes exactly the FP32 path on the RNE-rounded c and a."""
     import torch
