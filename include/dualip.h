@@ -144,8 +144,8 @@ typedef struct {
  * launch.  Beyond that the histogram rows are cut into n_windows equal windows
  * that fit in LDS beside the duals, and a gradient pass is one launch per
  * window: each recomputes x and keeps the sums of its own rows (the result is
- * bitwise the same; the data is read n_windows times).  Such problems use the
- * four-family kernel and cannot join a batch.
+ * bitwise the same; the data is read n_windows times).  Such problems use a
+ * multi-family kernel and cannot join a batch.
  * Synchronises the stream before returning.
  */
 dl_status dl_problem_create(const dl_problem_desc* desc, dl_problem** out);
