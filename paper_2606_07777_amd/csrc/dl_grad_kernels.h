@@ -509,7 +509,10 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
       theta = m1 - z;                    // the leader alone carries mass z
       done = true;
     } else {
-      theta = m1 - z;                    // f(m1 - z) >= 0: left of the root
+      // start left of the root, as close as the pass's sums allow: the root is at least
+      // (sum of any k entries - z) / k, here for k = 1 (the leader), k = 2 (the two
+      // leaders, both above that value since m1 - m2 < z) and k = #positive
+      theta = fmaxf(m1 - z, 0.5f * (m1 + m2 - z));
       if (sp > z) theta = fmaxf(theta, (sp - z) * __builtin_amdgcn_rcpf(cp));  // Newton step from 0
       done = false;
     }
