@@ -76,6 +76,18 @@ def test_unsupported_shapes_and_options(dl, base, wl):
         make(dl, wide)
 
 
+def test_batch_rejects_a_problem_twice(dl, base):
+    """Members keep per-pass state (fixed-point scales, partial slots) in their problem, so
+    one problem cannot be two members; mixed kernel variants are refused too."""
+    import dataclasses as dc
+    p = make(dl, base)
+    with pytest.raises(RuntimeError, match="twice"):
+        dl.Batch([p, p])
+    one = make(dl, dc.replace(base, n_families=1, a=None, b=base.b[:1], eq_families=0))
+    with pytest.raises(RuntimeError):
+        dl.Batch([p, one])
+
+
 def test_bad_call_arguments(dl, base):
     import torch
     p = make(dl, base)
