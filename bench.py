@@ -418,6 +418,11 @@ def batch_bench(args):
     work_b = sum(n * s["iters"] for n, s in zip(nnz, st_b))
     work_s = sum(n * s["iters"] for n, s in zip(nnz, st_s))
     same = all(a["iters"] == b["iters"] == c["iters"] == d["iters"] for a, b, c, d in zip(st_b, st_s, st_t, st_st))
+    for k, (a, b, c, d) in enumerate(zip(st_b, st_s, st_t, st_st)):
+        if not a["iters"] == b["iters"] == c["iters"] == d["iters"]:
+            log(f"member {k}: iterations batch {a['iters']} (gap {a['rel_gap']:.9e}), solo {b['iters']} "
+                f"(gap {b['rel_gap']:.9e}), batch cost-model {c['iters']} (gap {c['rel_gap']:.9e}), "
+                f"solo tuned {d['iters']} (gap {d['rel_gap']:.9e})")
     out = {"metric": "time to a 1e-4 gap for every member of the uneven batch", "unit": "s",
            "batch_s": t_batch, "batch_cost_model_s": t_model, "batch_tuner": tune,
            "solo_sequential_s": t_solo, "speedup": t_solo / t_batch,

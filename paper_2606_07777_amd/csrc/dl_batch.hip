@@ -20,19 +20,21 @@
 #include <chrono>
 #include <numeric>
 
+#include "dl_cert.h"
 #include "dl_common.h"
 #include "dl_split.h"
 
 struct dl_solver;  // dl_solver.hip
-dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag);
-dl_status dl_solver_certificate_enqueue(dl_solver* S);
-dl_status dl_solver_certificate_read(dl_solver* S, dl_solve_stats* out);
+dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag,
+                          double** ax);
+dl_status dl_cert_stats(const double* c, int flag, double gamma, int eq_mask, dl_solve_stats* st);
 
 namespace {
 
 struct bupd {
   const unsigned long long* part;
   unsigned long long* acc;  // the member's reduced sums (its problem's accumulator, zero between passes)
+  double* cert_ax;          // the certificate's A x (its solver's scratch)
   int n_slot;
   int mJ, J;        // item rows m*J, items J
   int nrow;         // dual rows: m*J, then the global-count row when present
@@ -103,6 +105,54 @@ __global__ void update_batch(const bupd* __restrict__ U, const bblk* __restrict_
   if (!isfinite(ln) || !isfinite(yn)) atomicOr(u.flag, 1);
 }
 
+// A check point of every live member at once.  The certificate's two passes
+// run as batched launches over the iteration's workgroup table; these kernels
+// do the rest: decode A x, the item part, and the final sums.
+struct bcert {
+  const double* ax;
+  const double* b;
+  const float* mu;  // the member's FP32 lam, the point both passes used
+  int m, J, eq_mask, glob;
+  const double* obj_part;   // per workgroup slot of the member
+  const double* pobj_part;
+  int n_slot;
+  float* rfac;
+  double* out;              // the member's 4 certificate values (device)
+  const int* flag;          // non-finite iterate flag
+};
+
+// A x of every live member from its reduced sums (the update's decode, without the step).
+__global__ void cert_decode_batch(const bupd* __restrict__ U, const bblk* __restrict__ blk) {
+  const bblk B = blk[blockIdx.x];
+  const bupd& u = U[B.inst];
+  const int r = B.r0 + (int)threadIdx.x;
+  if (r >= u.nrow) return;
+  const long long acc = (long long)u.acc[r];
+  u.acc[r] = 0ull;
+  const int k = r < u.mJ ? r / u.J : DL_MAX_FAMILIES;
+  u.cert_ax[r] = (double)acc / (double)u.qs[k];
+}
+
+// The certificate's item part, one workgroup per live member.
+__global__ void __launch_bounds__(1024) cert_items_batch(const bcert* __restrict__ C) {
+  __shared__ double sh[1024];
+  const bcert& c = C[blockIdx.x];
+  cert_items_body(c.ax, c.b, c.mu, c.m, c.J, c.eq_mask, c.glob, c.obj_part, c.n_slot, c.rfac, c.out, sh);
+}
+
+// The repaired primal value, then each member's 4 values and its flag, gathered
+// for one copy to the host (5 doubles per live member).
+__global__ void __launch_bounds__(1024) cert_final_batch(const bcert* __restrict__ C, double* __restrict__ res) {
+  __shared__ double sh[1024];
+  const bcert& c = C[blockIdx.x];
+  cert_final_body(c.pobj_part, c.n_slot, c.out, sh);
+  if (threadIdx.x == 0) {
+    double* o = res + 5 * (size_t)blockIdx.x;
+    for (int k = 0; k < 4; ++k) o[k] = c.out[k];
+    o[4] = (double)*c.flag;
+  }
+}
+
 }  // namespace
 
 struct dl_batch {
@@ -114,17 +164,29 @@ struct dl_batch {
   int wg_per_cu = 4;
   // device tables
   dl_grad_args* d_args = nullptr;
+  dl_grad_args* d_cargs = nullptr;  // the certificate's histogram + objective pass (at lam)
+  dl_grad_args* d_rargs = nullptr;  // the certificate's repair pass
+  bcert* d_cert = nullptr;          // per live position
+  double* d_cres = nullptr;         // 5 per live position
+  double* h_cres = nullptr;         // pinned copy of d_cres
+  size_t lds_rep = 0;
   dl_wg_desc* d_wgs = nullptr;
   bupd* d_upd = nullptr;
   bblk* d_blk = nullptr;
   bred* d_red = nullptr;
   unsigned long long* d_part = nullptr;
   size_t part_cap = 0;
+  // the certificate's per-workgroup objective sums (histogram pass, repair pass): a
+  // member's region has one entry per workgroup the batch deals it, which can exceed
+  // the slots its problem allocated for its own grid
+  double* d_obj = nullptr;
+  size_t obj_cap = 0;
   int n_wg = 0, n_blk = 0, n_red = 0;
   size_t lds = 0;
   bool glob = false;  // some live member has a global-count row
   // host mirrors
-  std::vector<dl_grad_args> h_args;
+  std::vector<dl_grad_args> h_args, h_cargs, h_rargs;
+  std::vector<bcert> h_cert;
   std::vector<dl_wg_desc> h_wgs;
   std::vector<bupd> h_upd;
   std::vector<bblk> h_blk;
@@ -143,9 +205,11 @@ struct dl_batch {
 static void free_batch(dl_batch* B) {
   if (!B) return;
   for (dl_solver* s : B->solvers) dl_solver_destroy(s);
-  void* ptrs[] = {B->d_args, B->d_wgs, B->d_upd, B->d_blk, B->d_red, B->d_part, B->d_clock};
+  void* ptrs[] = {B->d_args, B->d_cargs, B->d_rargs, B->d_cert, B->d_cres, B->d_obj,
+                  B->d_wgs,  B->d_upd,   B->d_blk,   B->d_red,  B->d_part, B->d_clock};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (B->h_cres) (void)hipHostFree(B->h_cres);
   delete B;
 }
 
@@ -215,7 +279,24 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     DL_HIP_TRY(hipMalloc((void**)&B->d_part, part_need * sizeof(unsigned long long)));
     B->part_cap = part_need;
   }
+  // objective slots: two per dealt workgroup (histogram pass, then repair pass)
+  std::vector<size_t> obj_off(live.size(), 0);
+  size_t obj_need = 0;
+  for (size_t q = 0; q < live.size(); ++q) {
+    obj_off[q] = obj_need;
+    obj_need += 2 * (size_t)std::max(1, w[q]);
+  }
+  if (obj_need > B->obj_cap) {
+    if (B->d_obj) DL_HIP_TRY(hipFree(B->d_obj));
+    B->d_obj = nullptr;
+    DL_HIP_TRY(hipMalloc((void**)&B->d_obj, obj_need * sizeof(double)));
+    B->obj_cap = obj_need;
+  }
   B->h_args.assign(B->n, dl_grad_args());
+  B->h_cargs.assign(B->n, dl_grad_args());
+  B->h_rargs.assign(B->n, dl_grad_args());
+  B->h_cert.clear();
+  size_t lds_rep = 0;
   B->live = live;
   B->wg_first.assign(live.size(), 0);
   for (size_t q = 0; q < live.size(); ++q) {
@@ -224,10 +305,38 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     double *lam, *y;
     float *mu_y, *mu_lam;
     int* flag;
-    DL_TRY(dl_solver_state(B->solvers[i], &lam, &y, &mu_y, &mu_lam, &flag));
+    double* cax;
+    DL_TRY(dl_solver_state(B->solvers[i], &lam, &y, &mu_y, &mu_lam, &flag, &cax));
     dl_grad_args A = dl_make_grad_args(P, mu_y, gamma);
     A.part = B->d_part + part_off[q];
     B->h_args[i] = A;
+    // the certificate's passes: same workgroup table and partial slots, at lam, with
+    // the batch's own objective slots
+    double* objs = B->d_obj + obj_off[q];
+    double* pobjs = objs + std::max(1, w[q]);
+    dl_grad_args C = A;
+    C.mu = mu_lam;
+    C.obj_part = objs;
+    B->h_cargs[i] = C;
+    C.rfac = P->rfac;
+    C.obj_part = pobjs;
+    B->h_rargs[i] = C;
+    lds_rep = std::max(lds_rep, dl_grad_lds_bytes(P, M_REPAIR));
+    bcert ce;
+    ce.ax = cax;
+    ce.b = P->b;
+    ce.mu = mu_lam;
+    ce.m = P->m;
+    ce.J = P->J;
+    ce.eq_mask = P->eq_mask;
+    ce.glob = P->glob;
+    ce.obj_part = objs;
+    ce.pobj_part = pobjs;
+    ce.n_slot = w[q];
+    ce.rfac = P->rfac;
+    ce.out = P->cert_out;
+    ce.flag = flag;
+    B->h_cert.push_back(ce);
     // contiguous task ranges of this instance with equal estimated time
     B->wg_first[q] = B->h_wgs.size();
     if (w[q] > 0) {
@@ -245,6 +354,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
     memset(&u, 0, sizeof(u));
     u.part = A.part;
     u.acc = P->acc;
+    u.cert_ax = cax;
     u.n_slot = w[q];
     u.mJ = P->m * P->J;
     u.nrow = (int)P->nrow();
@@ -269,6 +379,7 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
   B->n_wg = (int)B->h_wgs.size();
   B->n_blk = (int)B->h_blk.size();
   B->n_red = (int)B->h_red.size();
+  B->lds_rep = lds_rep;
   B->lds = lds;
   B->glob = false;
   for (int i : live) B->glob = B->glob || B->probs[i]->glob;
@@ -286,6 +397,11 @@ static dl_status build_tables(dl_batch* B, const std::vector<int>& live, double 
   DL_HIP_TRY(hipMalloc((void**)&B->d_red, sizeof(bred) * std::max<size_t>(1, B->h_red.size())));
   hipStream_t st = B->stream;
   DL_HIP_TRY(hipMemcpyAsync(B->d_args, B->h_args.data(), sizeof(dl_grad_args) * B->n, hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipMemcpyAsync(B->d_cargs, B->h_cargs.data(), sizeof(dl_grad_args) * B->n, hipMemcpyHostToDevice, st));
+  DL_HIP_TRY(hipMemcpyAsync(B->d_rargs, B->h_rargs.data(), sizeof(dl_grad_args) * B->n, hipMemcpyHostToDevice, st));
+  if (!B->h_cert.empty())
+    DL_HIP_TRY(hipMemcpyAsync(B->d_cert, B->h_cert.data(), sizeof(bcert) * B->h_cert.size(), hipMemcpyHostToDevice,
+                              st));
   if (!B->h_wgs.empty())
     DL_HIP_TRY(hipMemcpyAsync(B->d_wgs, B->h_wgs.data(), sizeof(dl_wg_desc) * B->h_wgs.size(), hipMemcpyHostToDevice,
                               st));
@@ -469,6 +585,37 @@ static void tuner_abort(dl_batch* B, loop_tuner& T) {
   }
 }
 
+// Certificates of every live member at once (the tables must be current): the
+// scale pass at lam, one batched histogram + objective pass, the slot
+// reduction, A x, the item part, one batched repair pass, the final sums, one
+// copy to the host.  stats[i] of each live member i gets its certificate and
+// status (DL_OK when it is finite; the gap test is the caller's).
+static dl_status batch_certify(dl_batch* B, double gamma, dl_solve_stats* stats, std::vector<dl_status>& cs) {
+  hipStream_t st = B->stream;
+  const int nl = (int)B->live.size();
+  const dl_problem* P0 = B->probs[B->live[0]];
+  DL_TRY(dl_launch_qscale_batch(B->d_cargs, B->n, st));
+  DL_TRY(dl_launch_grad_batch(P0, B->n_wg, B->d_cargs, B->d_wgs, B->lds, st, M_HIST | M_OBJ | (B->glob ? M_GLOB : 0)));
+  if (B->n_red > 0) hipLaunchKernelGGL(reduce_batch, dim3(B->n_red), dim3(256), 0, st, B->d_upd, B->d_red);
+  hipLaunchKernelGGL(cert_decode_batch, dim3(B->n_blk), dim3(256), 0, st, B->d_upd, B->d_blk);
+  hipLaunchKernelGGL(cert_items_batch, dim3(nl), dim3(1024), 0, st, B->d_cert);
+  DL_HIP_TRY(hipGetLastError());
+  DL_TRY(dl_launch_grad_batch(P0, B->n_wg, B->d_rargs, B->d_wgs, B->lds_rep, st, M_REPAIR));
+  hipLaunchKernelGGL(cert_final_batch, dim3(nl), dim3(1024), 0, st, B->d_cert, B->d_cres);
+  DL_HIP_TRY(hipGetLastError());
+  DL_HIP_TRY(hipMemcpyAsync(B->h_cres, B->d_cres, sizeof(double) * 5 * (size_t)nl, hipMemcpyDeviceToHost, st));
+  DL_HIP_TRY(hipStreamSynchronize(st));
+  cs.assign(B->n, DL_OK);
+  for (int q = 0; q < nl; ++q) {
+    const int i = B->live[q];
+    memset(&stats[i], 0, sizeof(stats[i]));
+    const double* c = B->h_cres + 5 * (size_t)q;
+    cs[i] = dl_cert_stats(c, c[4] != 0.0, gamma, B->probs[i]->eq_mask, &stats[i]);
+    stats[i].status = cs[i];
+  }
+  return DL_OK;
+}
+
 extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_batch** out) {
   DL_CHECK_ARG(out, "out is NULL");
   *out = nullptr;
@@ -518,8 +665,13 @@ extern "C" dl_status dl_batch_create(int32_t n, dl_problem* const* probs, dl_bat
     dl_set_error("hipDeviceGetAttribute failed");
     return fail(DL_EHIP);
   }
-  if (hipMalloc((void**)&B->d_args, sizeof(dl_grad_args) * n) != hipSuccess) {
-    dl_set_error("device allocation failed");
+  if (hipMalloc((void**)&B->d_args, sizeof(dl_grad_args) * n) != hipSuccess ||
+      hipMalloc((void**)&B->d_cargs, sizeof(dl_grad_args) * n) != hipSuccess ||
+      hipMalloc((void**)&B->d_rargs, sizeof(dl_grad_args) * n) != hipSuccess ||
+      hipMalloc((void**)&B->d_cert, sizeof(bcert) * n) != hipSuccess ||
+      hipMalloc((void**)&B->d_cres, sizeof(double) * 5 * n) != hipSuccess ||
+      hipHostMalloc((void**)&B->h_cres, sizeof(double) * 5 * n, hipHostMallocDefault) != hipSuccess) {
+    dl_set_error("device or pinned host allocation failed");
     return fail(DL_ENOMEM);
   }
   *out = B;
@@ -608,7 +760,8 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
       }
       rc = dl_launch_qscale_batch(B->d_args, B->n, B->stream);
       if (rc != DL_OK) break;
-      rc = dl_launch_grad_batch(B->probs[live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream, B->glob);
+      rc = dl_launch_grad_batch(B->probs[live[0]], B->n_wg, B->d_args, B->d_wgs, B->lds, B->stream,
+                                M_HIST | (B->glob ? M_GLOB : 0));
       if (rc != DL_OK) break;
       const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * tk * tk));
       const double beta = (tk - 1.0) / tn;
@@ -630,21 +783,13 @@ extern "C" dl_status dl_batch_solve(dl_batch* B, const dl_solve_opts* o, const d
         if (rc != DL_OK) break;
       }
       if (last && o->check_every > 0 && k % o->check_every == 0) {
-        // every live member's certificate on the stream, one synchronisation
-        std::vector<dl_status> enq(B->n, DL_OK);
-        for (int i : live) enq[i] = dl_solver_certificate_enqueue(B->solvers[i]);
-        if (hipStreamSynchronize(B->stream) != hipSuccess) {
-          dl_set_error("hipStreamSynchronize failed");
-          rc = DL_EHIP;
-          break;
-        }
+        // every live member's certificate in batched launches, one synchronisation
+        std::vector<dl_status> cst;
+        rc = batch_certify(B, gamma, stats, cst);
+        if (rc != DL_OK) break;
         std::vector<int> keep;
         for (int i : live) {
-          dl_status cs = enq[i] != DL_OK ? enq[i] : dl_solver_certificate_read(B->solvers[i], &stats[i]);
-          if (enq[i] != DL_OK) {
-            memset(&stats[i], 0, sizeof(stats[i]));
-            stats[i].status = enq[i];
-          }
+          const dl_status cs = cst[i];
           ++checks[i];
           if (cs != DL_OK) {
             stats[i].status = cs;

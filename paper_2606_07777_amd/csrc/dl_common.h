@@ -220,9 +220,10 @@ dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamm
 // Task ranges of n_wg workgroups with equal cost-model weight.
 std::vector<int64_t> dl_model_partition(const dl_problem* P, int n_wg);
 dl_status dl_set_partition(dl_problem* P, const std::vector<int64_t>& bounds);
-// glob: some member has a global-count row (runs the kernel that also counts sum x)
+// mode: M_HIST (| M_GLOB when some member has a global-count row) for an iteration,
+// M_HIST | M_OBJ (| M_GLOB) and M_REPAIR for the certificate's two passes
 dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
-                               size_t lds, hipStream_t st, bool glob);
+                               size_t lds, hipStream_t st, int mode);
 dl_status dl_grad_prepare(const dl_problem* P);
 // Fixed-point scales for a histogram pass at gather point mu (into P->qs_dev),
 // and the same for every instance of a batched pass (one block per entry).

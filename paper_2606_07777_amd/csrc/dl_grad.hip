@@ -37,7 +37,7 @@
 #define DL_GV_DECL(mf, a, bf)                                                                              \
   dl_status dl_grad_launch_v_##mf##_##a##_##bf(const dl_problem*, int, const dl_grad_args&, size_t);       \
   dl_status dl_grad_batch_v_##mf##_##a##_##bf(const dl_problem*, int, const dl_grad_args*, const dl_wg_desc*, \
-                                              size_t, hipStream_t, bool);                                   \
+                                              size_t, hipStream_t, int);                                    \
   void dl_grad_attr_v_##mf##_##a##_##bf();
 DL_GV_DECL(1, 0, 0)
 DL_GV_DECL(1, 0, 1)
@@ -191,20 +191,20 @@ dl_status dl_grad_prepare(const dl_problem* P) {
 }
 
 dl_status dl_launch_grad_batch(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
-                               size_t lds, hipStream_t st, bool glob) {
+                               size_t lds, hipStream_t st, int mode) {
   if (n_wg <= 0) return DL_OK;
   const bool bf = P->storage == DL_BF16;
   if (P->mf == 1 && !P->has_a)
-    return bf ? dl_grad_batch_v_1_0_1(P, n_wg, d_args, d_wgs, lds, st, glob)
-              : dl_grad_batch_v_1_0_0(P, n_wg, d_args, d_wgs, lds, st, glob);
+    return bf ? dl_grad_batch_v_1_0_1(P, n_wg, d_args, d_wgs, lds, st, mode)
+              : dl_grad_batch_v_1_0_0(P, n_wg, d_args, d_wgs, lds, st, mode);
   if (P->mf == 1)
-    return bf ? dl_grad_batch_v_1_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
-              : dl_grad_batch_v_1_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
+    return bf ? dl_grad_batch_v_1_1_1(P, n_wg, d_args, d_wgs, lds, st, mode)
+              : dl_grad_batch_v_1_1_0(P, n_wg, d_args, d_wgs, lds, st, mode);
   if (P->mf == 2)
-    return bf ? dl_grad_batch_v_2_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
-              : dl_grad_batch_v_2_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
-  return bf ? dl_grad_batch_v_4_1_1(P, n_wg, d_args, d_wgs, lds, st, glob)
-            : dl_grad_batch_v_4_1_0(P, n_wg, d_args, d_wgs, lds, st, glob);
+    return bf ? dl_grad_batch_v_2_1_1(P, n_wg, d_args, d_wgs, lds, st, mode)
+              : dl_grad_batch_v_2_1_0(P, n_wg, d_args, d_wgs, lds, st, mode);
+  return bf ? dl_grad_batch_v_4_1_1(P, n_wg, d_args, d_wgs, lds, st, mode)
+            : dl_grad_batch_v_4_1_0(P, n_wg, d_args, d_wgs, lds, st, mode);
 }
 
 dl_grad_args dl_make_grad_args(const dl_problem* P, const float* mu, double gamma) {

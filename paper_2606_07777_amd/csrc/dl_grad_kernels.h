@@ -980,14 +980,25 @@ dl_status launch_mode(const dl_problem* P, int mode, const dl_grad_args& A, size
 
 template <int MF, bool HAS_A, int KMAX, typename TV>
 dl_status launch_batch_t(const dl_problem* P, int n_wg, const dl_grad_args* d_args, const dl_wg_desc* d_wgs,
-                         size_t lds, hipStream_t st, bool glob) {
+                         size_t lds, hipStream_t st, int mode) {
   (void)P;
-  if (glob)
-    hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB>), dim3(n_wg), dim3(DL_WG), lds, st,
-                       d_args, d_wgs);
-  else
-    hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST>), dim3(n_wg), dim3(DL_WG), lds, st, d_args,
-                       d_wgs);
+  // the iteration's histogram pass, and the certificate's two passes
+  switch (mode) {
+#define DL_BATCH_CASE(MD)                                                                                 \
+  case MD:                                                                                                \
+    hipLaunchKernelGGL((grad_pass_batch<MF, HAS_A, KMAX, TV, MD>), dim3(n_wg), dim3(DL_WG), lds, st, d_args, \
+                       d_wgs);                                                                            \
+    break;
+    DL_BATCH_CASE(M_HIST)
+    DL_BATCH_CASE(M_HIST | M_GLOB)
+    DL_BATCH_CASE(M_HIST | M_OBJ)
+    DL_BATCH_CASE(M_HIST | M_OBJ | M_GLOB)
+    DL_BATCH_CASE(M_REPAIR)
+#undef DL_BATCH_CASE
+    default:
+      dl_set_error("internal: unknown batched gradient-pass mode");
+      return DL_EINVAL;
+  }
   DL_HIP_TRY(hipGetLastError());
   return DL_OK;
 }
@@ -1008,6 +1019,12 @@ void set_attr_all() {
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_XOUT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass_batch<MF, HAS_A, KMAX, TV, M_HIST | M_OBJ | M_GLOB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void*)grad_pass_batch<MF, HAS_A, KMAX, TV, M_REPAIR>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
   (void)hipFuncSetAttribute((const void*)grad_pass<MF, HAS_A, KMAX, TV, M_HIST | M_GLOB>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, big);

@@ -25,8 +25,8 @@ dl_status DL_GV_FN(dl_grad_launch_v)(const dl_problem* P, int mode, const dl_gra
 }
 
 dl_status DL_GV_FN(dl_grad_batch_v)(const dl_problem* P, int n_wg, const dl_grad_args* d_args,
-                                    const dl_wg_desc* d_wgs, size_t lds, hipStream_t st, bool glob) {
-  return launch_batch_t<GV_MF, GV_A, GV_KMAX, GV_TV>(P, n_wg, d_args, d_wgs, lds, st, glob);
+                                    const dl_wg_desc* d_wgs, size_t lds, hipStream_t st, int mode) {
+  return launch_batch_t<GV_MF, GV_A, GV_KMAX, GV_TV>(P, n_wg, d_args, d_wgs, lds, st, mode);
 }
 
 void DL_GV_FN(dl_grad_attr_v)() { set_attr_all<GV_MF, GV_A, GV_KMAX, GV_TV>(); }

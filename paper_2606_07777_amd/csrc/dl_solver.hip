@@ -11,6 +11,7 @@
 #include <mutex>
 #include <utility>
 
+#include "dl_cert.h"
 #include "dl_common.h"
 
 namespace {
@@ -121,86 +122,17 @@ __global__ void to_f32(const double* in, int n, float* out) {
   if (r < n) out[r] = (float)in[r];
 }
 
-// Deterministic block reduction helpers (fixed tree over 1024 threads).
-__device__ double block_sum(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
-  }
-  double r = sh[0];
-  __syncthreads();
-  return r;
-}
-__device__ double block_max(double v, double* sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
-    __syncthreads();
-  }
-  double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-// Certificate, item part (one workgroup): repair factor r_j =
-// rho min_k min(1, b_kj / (A_k x)_j), with rho = min(1, M / sum x) for a
-// global-count row (1 without one), max slack, lam.b and -lam.(Ax - b) at the
-// FP32 point mu the pass used, and the Lagrangian sum over workgroups.
-//   out[0] = sum_w obj_part[w] - mu.b   (dual value g(mu))
-//   out[1] = max_r (A x - b)_r^+
-//   out[2] = -mu.(A x - b)
+// Certificate, item part (one workgroup): see cert_items_body.
 __global__ void cert_items(const double* ax, const double* b, const float* mu, int m, int J, int eq_mask, int glob,
                            const double* obj_part, int n_wg, float* rfac, double* out) {
   __shared__ double sh[1024];
-  const int mJ = m * J;
-  double lb = 0.0, slack = 0.0, lg = 0.0, rho = 1.0;
-  if (glob) {
-    const double G = ax[mJ], M = b[mJ];
-    if (G > M) rho = M > 0.0 ? M / G : 0.0;
-    if (threadIdx.x == 0) {
-      slack = G - M;
-      lb = (double)mu[mJ] * M;
-      lg = -(double)mu[mJ] * (G - M);
-    }
-  }
-  for (int j = threadIdx.x; j < J; j += blockDim.x) {
-    double rj = rho;
-    for (int k = 0; k < m; ++k) {
-      const int r = k * J + j;
-      const double viol = ax[r] - b[r];
-      const bool eq = (eq_mask >> k) & 1;
-      slack = fmax(slack, eq ? fabs(viol) : viol);
-      lb += (double)mu[r] * b[r];
-      lg -= (double)mu[r] * viol;
-      if (!eq && ax[r] > b[r]) rj = fmin(rj, b[r] > 0.0 ? rho * (b[r] / ax[r]) : 0.0);
-    }
-    rfac[j] = (float)rj;
-  }
-  double os = 0.0;
-  for (int w = threadIdx.x; w < n_wg; w += blockDim.x) os += obj_part[w];
-  lb = block_sum(lb, sh);
-  lg = block_sum(lg, sh);
-  os = block_sum(os, sh);
-  slack = block_max(slack, sh);
-  if (threadIdx.x == 0) {
-    out[0] = os - lb;
-    out[1] = slack;
-    out[2] = lg;
-  }
+  cert_items_body(ax, b, mu, m, J, eq_mask, glob, obj_part, n_wg, rfac, out, sh);
 }
 
 // out[3] = sum_w pobj_part[w]   (primal value of the repaired point)
 __global__ void cert_final(const double* pobj_part, int n_wg, double* out) {
   __shared__ double sh[1024];
-  double s = 0.0;
-  for (int w = threadIdx.x; w < n_wg; w += blockDim.x) s += pobj_part[w];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[3] = s;
+  cert_final_body(pobj_part, n_wg, out, sh);
 }
 
 inline unsigned blocks_for(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -215,6 +147,8 @@ dl_status launch_reduce(const dl_problem* P) {
 }
 
 }  // namespace
+
+dl_status dl_cert_stats(const double* c, int flag, double gamma, int eq_mask, dl_solve_stats* st);
 
 struct dl_solver {
   dl_problem* P = nullptr;
@@ -291,24 +225,9 @@ dl_status certificate_enqueue(dl_solver* S) {
 dl_status certificate_read(dl_solver* S, dl_solve_stats* st) {
   dl_problem* P = S->P;
   const int hflag = *reinterpret_cast<const int*>(P->cert_host + 8);
-  const double g = P->cert_host[0], pobj = P->cert_host[3];
-  st->gamma = S->gamma;
-  st->dual_obj = g;
-  st->primal_obj = pobj;
-  // equality rows have no feasible repair: the certified gap is undefined
-  st->rel_gap = P->eq_mask ? NAN : (pobj - g) / fmax(1.0, fabs(g));
-  st->max_slack = P->cert_host[1];
-  st->lagr_gap = P->cert_host[2];
+  const dl_status rc = dl_cert_stats(P->cert_host, hflag, S->gamma, P->eq_mask, st);
   st->iters = S->iters;
-  if (hflag) {
-    dl_set_error("non-finite dual iterate");
-    return DL_DIVERGED;
-  }
-  if (!isfinite(g) || !isfinite(pobj)) {
-    dl_set_error("non-finite dual objective or certificate");
-    return DL_NUMERIC;
-  }
-  return DL_OK;
+  return rc;
 }
 
 dl_status certificate(dl_solver* S, dl_solve_stats* st) {
@@ -319,15 +238,28 @@ dl_status certificate(dl_solver* S, dl_solve_stats* st) {
 
 }  // namespace
 
-// Split certificate for callers that check many solvers on one stream: enqueue
-// each, synchronise once, then read each.
-dl_status dl_solver_certificate_enqueue(dl_solver* S) { return certificate_enqueue(S); }
-dl_status dl_solver_certificate_read(dl_solver* S, dl_solve_stats* out) {
-  memset(out, 0, sizeof(*out));
-  const dl_status s = certificate_read(S, out);
-  out->status = s;
-  return s;
+// Statistics of a certificate from its four values (dual value, max slack,
+// Lagrangian gap, repaired primal value) and the iterate's non-finite flag.
+dl_status dl_cert_stats(const double* c, int flag, double gamma, int eq_mask, dl_solve_stats* st) {
+  const double g = c[0], pobj = c[3];
+  st->gamma = gamma;
+  st->dual_obj = g;
+  st->primal_obj = pobj;
+  // equality rows have no feasible repair: the certified gap is undefined
+  st->rel_gap = eq_mask ? NAN : (pobj - g) / fmax(1.0, fabs(g));
+  st->max_slack = c[1];
+  st->lagr_gap = c[2];
+  if (flag) {
+    dl_set_error("non-finite dual iterate");
+    return DL_DIVERGED;
+  }
+  if (!isfinite(g) || !isfinite(pobj)) {
+    dl_set_error("non-finite dual objective or certificate");
+    return DL_NUMERIC;
+  }
+  return DL_OK;
 }
+
 
 // ---------------------------------------------------------------------------
 // ObjectiveFunction and ProjectionMap
@@ -402,8 +334,10 @@ extern "C" dl_status dl_solver_create(dl_problem* P, const double* lambda0, dl_s
 }
 
 // Device state of a solver, for the batched iteration.
-dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag) {
+dl_status dl_solver_state(dl_solver* S, double** lam, double** y, float** mu_y, float** mu_lam, int** flag,
+                          double** ax) {
   DL_CHECK_ARG(S, "NULL solver");
+  if (ax) *ax = S->ax;
   *lam = S->lam;
   *y = S->y;
   *mu_y = S->mu_y;

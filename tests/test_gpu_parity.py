@@ -646,9 +646,74 @@ def test_batch_matches_solo_solves(dl, orc, wl):
               f"solo {st_s['iters']} gap {st_b[k]['rel_gap']:.2e}")
         assert st_b[k]["iters"] == st_s["iters"]
         assert np.array_equal(lam_b[k].cpu().numpy(), lam_s.cpu().numpy())
+        _same_certificate(st_b[k], st_s)
     lo, so, _, _ = orc.solve(members[0], sched["gammas"], sched["iters"], tol=1e-4, max_iters=3000,
                              check_every=10, jacobi=True)
     assert abs(st_b[0]["dual_obj"] - so["dual_obj"]) <= 2e-4 * abs(so["dual_obj"])
+
+
+def _same_certificate(a, b):
+    """The batch computes a member's certificate in batched launches over its own
+    workgroup split; at the same lam it matches the solo certificate up to the order
+    of the per-workgroup FP64 objective sums (the A x sums are integers: slack and
+    Lagrangian gap agree exactly)."""
+    for key in ("dual_obj", "primal_obj"):
+        assert abs(a[key] - b[key]) <= 1e-12 * max(1.0, abs(b[key])), (key, a[key], b[key])
+    assert abs(a["rel_gap"] - b["rel_gap"]) <= 1e-12 or (np.isnan(a["rel_gap"]) and np.isnan(b["rel_gap"]))
+    assert a["max_slack"] == b["max_slack"] and a["lagr_gap"] == b["lagr_gap"]
+
+
+def test_batch_certificates_with_global_and_equality_rows(dl, wl):
+    """Check points of a batch whose members carry a global-count row, an equality
+    family, or neither: iteration counts, lam and certificates as in the solo solves."""
+    import dataclasses
+    members = []
+    for k in range(3):
+        m = wl.random_small(340 + k, 3000 + 800 * k, 80, 30, n_families=2, a_ones=True, b_scale=0.1)
+        if k == 0:
+            m = dataclasses.replace(m, global_cap=0.3 * m.n_users)
+        elif k == 1:
+            deg = np.diff(m.row_ptr)
+            x0 = np.repeat(0.9 / np.maximum(deg, 1), deg)
+            b = m.b.copy()
+            b[1] = np.bincount(m.item_idx, weights=m.a[1].astype(np.float64) * x0, minlength=m.n_items)
+            m = dataclasses.replace(m, b=b, eq_families=0b10)
+        members.append(m)
+    sched = dict(gammas=[1e-1, 1e-2], iters=[60, -1], tol=1e-4, max_iters=1500, check_every=10)
+    probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]
+    lam_b, st_b = dl.Batch(probs).solve(**sched)
+    for k, p in enumerate(probs):
+        lam_s, st_s = p.solve(**sched)
+        print(f"member {k}: iters batch {st_b[k]['iters']} solo {st_s['iters']} gap {st_b[k]['rel_gap']:.3e} "
+              f"status {st_b[k]['status']}")
+        assert st_b[k]["iters"] == st_s["iters"] and st_b[k]["status"] == st_s["status"]
+        assert np.array_equal(lam_b[k].cpu().numpy(), lam_s.cpu().numpy())
+        _same_certificate(st_b[k], st_s)
+
+
+def test_batch_leaves_its_problems_intact(dl, wl):
+    """The batch deals a small member more workgroups than its own grid has slots
+    (here about 190 against 12); the certificate's per-workgroup sums must then go to
+    the batch's own storage.  After a batched solve with check points, every member's
+    problem still computes bitwise what a freshly created copy computes."""
+    import torch
+    members = [wl.random_small(350 + k, 3000 + 800 * k, 80, 30, b_scale=0.1) for k in range(3)]
+    sched = dict(gammas=[1e-1, 1e-2], iters=[40, -1], tol=1e-4, max_iters=600, check_every=10)
+    probs = [dl.Problem.from_instance(m, jacobi=True) for m in members]
+    assert all(p.info()["n_workgroups"] < 64 for p in probs)
+    dl.Batch(probs).solve(**sched)
+    rng = np.random.default_rng(5)
+    for m, p in zip(members, probs):
+        fresh = dl.Problem.from_instance(m, jacobi=True)
+        lam = torch.from_numpy(np.abs(rng.normal(size=p.nrow)) * 0.05)
+        g1, grad1, x1 = p.dual_grad(lam, 1e-2, want_x=True)
+        g2, grad2, x2 = fresh.dual_grad(lam, 1e-2, want_x=True)
+        assert np.array_equal(grad1.cpu().numpy(), grad2.cpu().numpy())
+        assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy()) and g1 == g2
+        l1, s1 = p.solve(**sched)
+        l2, s2 = fresh.solve(**sched)
+        assert np.array_equal(l1.cpu().numpy(), l2.cpu().numpy()) and s1["iters"] == s2["iters"]
+        _same_certificate(s1, s2)
 
 
 def test_tuned_batch_matches_solo(dl, wl):
