@@ -275,9 +275,10 @@ typedef struct {
   int64_t n_grad;          /* timed gradient passes */
   double grad_ms_total;    /* summed HIP-event durations of those passes */
   int64_t n_update;
-  double update_ms_total;
+  double update_ms_total;  /* summed time from each pass's end to the end of its reduction and update */
 } dl_timing;
-/* Brackets every later gradient pass and update with HIP events on the stream. */
+/* Brackets every later gradient pass with HIP events on the stream, and closes
+ * each reduction + update with one more (three events per iteration). */
 dl_status dl_solver_enable_timing(dl_solver* s, int32_t on);
 /* Synchronises and returns the sums since timing was enabled. */
 dl_status dl_solver_get_timing(dl_solver* s, dl_timing* out);

@@ -161,7 +161,10 @@ struct dl_solver {
   double gamma = 1.0, eta = 1.0, tk = 1.0;
   int64_t iters = 0;
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_grad, ev_upd;
+  // timing: (start, end) of each gradient pass, and the end of the reduction +
+  // update that follows it (which starts at the pass's end event)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_grad;
+  std::vector<hipEvent_t> ev_upd;
   size_t n_ev_grad = 0, n_ev_upd = 0;
 };
 
@@ -191,6 +194,16 @@ dl_status next_event_pair(std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, siz
     v.emplace_back(a, b);
   }
   *out = &v[n++];
+  return DL_OK;
+}
+
+dl_status next_event(std::vector<hipEvent_t>& v, size_t& n, hipEvent_t* out) {
+  if (n == v.size()) {
+    hipEvent_t a;
+    DL_HIP_TRY(hipEventCreate(&a));
+    v.push_back(a);
+  }
+  *out = v[n++];
   return DL_OK;
 }
 
@@ -355,10 +368,7 @@ extern "C" void dl_solver_destroy(dl_solver* S) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
-  for (auto& e : S->ev_upd) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
+  for (hipEvent_t e : S->ev_upd) (void)hipEventDestroy(e);
   delete S;
 }
 
@@ -399,11 +409,10 @@ extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
       DL_HIP_TRY(hipEventRecord(eg->first, P->stream));
     }
     DL_TRY(dl_launch_grad(P, M_HIST, S->mu_y, S->gamma, nullptr, nullptr, nullptr, nullptr, true));
-    std::pair<hipEvent_t, hipEvent_t>* eu = nullptr;
+    hipEvent_t eu = nullptr;
     if (S->timing) {
       DL_HIP_TRY(hipEventRecord(eg->second, P->stream));
-      DL_TRY(next_event_pair(S->ev_upd, S->n_ev_upd, &eu));
-      DL_HIP_TRY(hipEventRecord(eu->first, P->stream));
+      DL_TRY(next_event(S->ev_upd, S->n_ev_upd, &eu));
     }
     // FISTA momentum: t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, beta = (t_k - 1) / t_{k+1}
     DL_TRY(launch_reduce(P));
@@ -412,7 +421,7 @@ extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
     S->tk = tn;
     hipLaunchKernelGGL(update_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
     DL_HIP_TRY(hipGetLastError());
-    if (S->timing) DL_HIP_TRY(hipEventRecord(eu->second, P->stream));
+    if (S->timing) DL_HIP_TRY(hipEventRecord(eu, P->stream));
     ++S->iters;
   }
   return DL_OK;
@@ -499,7 +508,7 @@ extern "C" dl_status dl_solver_get_timing(dl_solver* S, dl_timing* out) {
   }
   for (size_t i = 0; i < S->n_ev_upd; ++i) {
     float ms = 0.f;
-    DL_HIP_TRY(hipEventElapsedTime(&ms, S->ev_upd[i].first, S->ev_upd[i].second));
+    DL_HIP_TRY(hipEventElapsedTime(&ms, S->ev_grad[i].second, S->ev_upd[i]));
     out->update_ms_total += ms;
   }
   out->n_grad = (int64_t)S->n_ev_grad;
