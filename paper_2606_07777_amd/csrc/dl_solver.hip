@@ -18,6 +18,7 @@ namespace {
 
 struct upd_args {
   unsigned long long* acc;  // reduced per-item sums (read and cleared)
+  const unsigned long long* part;  // per-workgroup partial sums, n_wg x nrow (the fused step reads them)
   int n_wg;
   int mJ, J;        // item rows m*J, items J
   int nrow;         // dual rows: m*J, then the global-count row when present
@@ -58,14 +59,12 @@ __device__ __forceinline__ double take_sum(unsigned long long* acc, int r) {
   return (double)v;
 }
 
-// Fused accelerated step: reduce the gradient at y', take
+// The accelerated step of row r from its reduced fixed-point sum: take
 // lam'_+ = max(0, y' + eta D (A x - b)), y'_+ = lam'_+ + beta (lam'_+ - lam'),
 // and publish the next gather point D y'_+ (FP32).
-__global__ void update_kernel(upd_args U) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= U.nrow) return;
+__device__ __forceinline__ void step_row(const upd_args& U, int r, long long sum) {
   const int k = r < U.mJ ? r / U.J : DL_MAX_FAMILIES;  // the global-count row has its own scale
-  const double ax = take_sum(U.acc, r) / (double)U.qs[k];
+  const double ax = (double)sum / (double)U.qs[k];
   const double Dr = U.D[r];
   const double gs = Dr * (ax - U.b[r]);
   const double lo = U.lam[r];
@@ -77,6 +76,30 @@ __global__ void update_kernel(upd_args U) {
   U.mu_y[r] = (float)(Dr * yn);
   U.mu_lam[r] = (float)(Dr * ln);
   if (!isfinite(ln) || !isfinite(yn)) atomicOr(U.flag, 1);
+}
+
+// Reduction and step in one launch: a block takes 64 dual rows; its 16 slices
+// of 64 lanes each add every 16th workgroup's partial sums of those rows
+// (512 contiguous bytes per slot and wavefront), the slices are added in LDS,
+// and one slice applies the step.  Integer sums: exact, so the result is the
+// two-launch reduction's bitwise.
+constexpr int DL_RU_ROWS = 64;
+constexpr int DL_RU_SLICES = 16;
+__global__ void __launch_bounds__(DL_RU_ROWS * DL_RU_SLICES) reduce_update_kernel(upd_args U) {
+  __shared__ long long sh[DL_RU_SLICES][DL_RU_ROWS];
+  const int rl = (int)threadIdx.x % DL_RU_ROWS;
+  const int sl = (int)threadIdx.x / DL_RU_ROWS;
+  const int r = (int)blockIdx.x * DL_RU_ROWS + rl;
+  long long sum = 0;
+  if (r < U.nrow) {
+#pragma unroll 4
+    for (int w = sl; w < U.n_wg; w += DL_RU_SLICES) sum += (long long)U.part[(size_t)w * U.nrow + r];
+  }
+  sh[sl][rl] = sum;
+  __syncthreads();
+  if (sl != 0 || r >= U.nrow) return;
+  for (int q = 1; q < DL_RU_SLICES; ++q) sum += sh[q][rl];
+  step_row(U, r, sum);
 }
 
 // A x (and A x - b) from the partials, no step.
@@ -174,6 +197,7 @@ upd_args make_upd(const dl_problem* P) {
   upd_args U;
   memset(&U, 0, sizeof(U));
   U.acc = P->acc;
+  U.part = P->part;
   U.n_wg = P->n_wg;
   U.mJ = P->m * P->J;
   U.nrow = (int)P->nrow();
@@ -415,11 +439,11 @@ extern "C" dl_status dl_solver_step(dl_solver* S, int64_t n) {
       DL_TRY(next_event(S->ev_upd, S->n_ev_upd, &eu));
     }
     // FISTA momentum: t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, beta = (t_k - 1) / t_{k+1}
-    DL_TRY(launch_reduce(P));
     const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * S->tk * S->tk));
     U.beta = (S->tk - 1.0) / tn;
     S->tk = tn;
-    hipLaunchKernelGGL(update_kernel, dim3(blocks_for(mJ)), dim3(256), 0, P->stream, U);
+    hipLaunchKernelGGL(reduce_update_kernel, dim3(blocks_for(mJ, DL_RU_ROWS)), dim3(DL_RU_ROWS * DL_RU_SLICES), 0,
+                       P->stream, U);
     DL_HIP_TRY(hipGetLastError());
     if (S->timing) DL_HIP_TRY(hipEventRecord(eu, P->stream));
     ++S->iters;
