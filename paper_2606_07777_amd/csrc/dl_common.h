@@ -171,6 +171,8 @@ struct dl_problem {
   unsigned* ext = nullptr;
   float* qs_dev = nullptr;   // fixed-point scales of the last histogram pass: the families', then
                              // the global-count row's at index DL_MAX_FAMILIES
+  unsigned* qs_words = nullptr;  // the scale kernel's pass-wide maxima (5 float bit patterns, zero between launches)
+  unsigned* qs_cnt = nullptr;    // its arrival counter (zero between launches)
 
   // reordered device layout
   int64_t* rp = nullptr;

@@ -64,79 +64,126 @@ namespace {
 // relative roundings fit the factor-2 headroom above 2^30).  The grid is as
 // fine as the pass allows and never coarser than for max|a_k| * radius.  One
 // block of 1024 lanes; deterministic.
-__device__ void qscale_body(const dl_grad_args& A, float* out) {
-  __shared__ float sh[1024];
+// The bound of item j: per family max|a_kj| xmax_j into bk[k], and xmax_j into bg
+// (maxima over the items a thread has seen).
+__device__ __forceinline__ void qscale_item(const dl_grad_args& A, int j, float mug, float (&bk)[DL_MAX_FAMILIES],
+                                            float& bg) {
   const int J = A.J, m = A.m;
   const float ig = -A.neg_inv_gamma;
   const float z = A.radius;
   const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
   const float ulp = 0x1p-24f * (float)(m + 5);
-  float bk[DL_MAX_FAMILIES] = {0.f, 0.f, 0.f, 0.f};
-  float bg = 0.f;  // global-count row: bound on x itself
-  const float mug = A.glob ? A.mu[(size_t)m * J] : 0.f;
-#pragma unroll 4
-  for (int j = threadIdx.x; j < J; j += blockDim.x) {
-    const unsigned ec = A.ext[j];
-    const float cneg = dl_ord_dec(ec), cabs = dl_ord_dec(A.ext[(size_t)J + j]);
-    // the global-count dual shifts every v by -mu_g / gamma
-    float t = cneg - mug, mag = cabs + fabsf(mug);
-    float aab[DL_MAX_FAMILIES];
-#pragma unroll
-    for (int k = 0; k < DL_MAX_FAMILIES; ++k) {
-      aab[k] = 0.f;
-      if (k < m) {
-        const int sl = A.a_slot[k];
-        const float amx = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(2 + 2 * sl) * J + j]) : 1.f;
-        const float ang = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(3 + 2 * sl) * J + j]) : -1.f;
-        const float mu = A.mu[(size_t)k * J + j];
-        t += mu >= 0.f ? ang * mu : amx * (-mu);
-        aab[k] = fmaxf(fabsf(amx), fabsf(ang));
-        mag += aab[k] * fabsf(mu);
-      }
-    }
-    // the bound itself in FP32: its own roundings are covered by the margin
-    const float v = t * ig;
-    const float xm = eq ? z : fminf(z, fmaxf(0.f, v) + ulp * (mag * ig + fabsf(v)) * 2.f);
-    const bool any = ec != DL_ORD_NEG_INF;  // some user is eligible for item j
-#pragma unroll
-    for (int k = 0; k < DL_MAX_FAMILIES; ++k)
-      if (k < m && any) bk[k] = fmaxf(bk[k], aab[k] * xm);
-    if (any) bg = fmaxf(bg, xm);
-  }
+  const unsigned ec = A.ext[j];
+  const float cneg = dl_ord_dec(ec), cabs = dl_ord_dec(A.ext[(size_t)J + j]);
+  // the global-count dual shifts every v by -mu_g / gamma
+  float t = cneg - mug, mag = cabs + fabsf(mug);
+  float aab[DL_MAX_FAMILIES];
 #pragma unroll
   for (int k = 0; k < DL_MAX_FAMILIES; ++k) {
-    if (k >= m) break;
-    sh[threadIdx.x] = bk[k];
+    aab[k] = 0.f;
+    if (k < m) {
+      const int sl = A.a_slot[k];
+      const float amx = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(2 + 2 * sl) * J + j]) : 1.f;
+      const float ang = sl >= 0 ? dl_ord_dec(A.ext[(size_t)(3 + 2 * sl) * J + j]) : -1.f;
+      const float mu = A.mu[(size_t)k * J + j];
+      t += mu >= 0.f ? ang * mu : amx * (-mu);
+      aab[k] = fmaxf(fabsf(amx), fabsf(ang));
+      mag += aab[k] * fabsf(mu);
+    }
+  }
+  // the bound itself in FP32: its own roundings are covered by the margin
+  const float v = t * ig;
+  const float xm = eq ? z : fminf(z, fmaxf(0.f, v) + ulp * (mag * ig + fabsf(v)) * 2.f);
+  const bool any = ec != DL_ORD_NEG_INF;  // some user is eligible for item j
+#pragma unroll
+  for (int k = 0; k < DL_MAX_FAMILIES; ++k)
+    if (k < m && any) bk[k] = fmaxf(bk[k], aab[k] * xm);
+  if (any) bg = fmaxf(bg, xm);
+}
+
+// The bounds of items [j0, j1) strided by the block, reduced over the block (every
+// thread ends with the maxima).
+__device__ void qscale_items(const dl_grad_args& A, int j0, int j1, float (&bk)[DL_MAX_FAMILIES], float& bg,
+                             float* sh) {
+#pragma unroll
+  for (int k = 0; k < DL_MAX_FAMILIES; ++k) bk[k] = 0.f;
+  bg = 0.f;  // global-count row: bound on x itself
+  const float mug = A.glob ? A.mu[(size_t)A.m * A.J] : 0.f;
+#pragma unroll 4
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) qscale_item(A, j, mug, bk, bg);
+  // block maxima (max is exact: the result does not depend on the split)
+#pragma unroll
+  for (int k = 0; k <= DL_MAX_FAMILIES; ++k) {
+    float v = k < DL_MAX_FAMILIES ? bk[k] : bg;
+    sh[threadIdx.x] = v;
     __syncthreads();
     for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
       if ((int)threadIdx.x < s2) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s2]);
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
-      const float B = sh[0] * (1.0f + 0x1p-16f);
-      float qv = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
-      qv = fminf(fmaxf(qv, A.qscale[k]), 0x1p60f);
-      out[k] = qv;
-    }
+    v = sh[0];
     __syncthreads();
+    if (k < DL_MAX_FAMILIES) bk[k] = v;
+    else bg = v;
+  }
+}
+
+// The scales from the pass-wide maxima (thread 0).
+__device__ void qscale_finish(const dl_grad_args& A, const float (&bk)[DL_MAX_FAMILIES], float bg, float* out) {
+  for (int k = 0; k < DL_MAX_FAMILIES && k < A.m; ++k) {
+    const float B = bk[k] * (1.0f + 0x1p-16f);
+    float qv = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
+    qv = fminf(fmaxf(qv, A.qscale[k]), 0x1p60f);
+    out[k] = qv;
   }
   if (A.glob) {
     // |x| <= B_g per element: each addend below 2^31 on the grid 2^(30 - ceil log2 B_g),
     // never coarser than for x <= radius; n_nonzeros * 2^31 < 2^63 bounds the sum
-    sh[threadIdx.x] = bg;
-    __syncthreads();
-    for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
-      if ((int)threadIdx.x < s2) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s2]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const float B = sh[0] * (1.0f + 0x1p-16f);
-      const float coarse = ldexpf(1.f, 30 - (int)ceilf(log2f(fmaxf(z, 0x1p-30f))));
-      float qv = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
-      out[DL_MAX_FAMILIES] = fminf(fmaxf(qv, coarse), 0x1p60f);
-    }
-    __syncthreads();
+    const float B = bg * (1.0f + 0x1p-16f);
+    const float coarse = ldexpf(1.f, 30 - (int)ceilf(log2f(fmaxf(A.radius, 0x1p-30f))));
+    float qv = B > 0.f ? ldexpf(1.f, 30 - (int)ceilf(log2f(B))) : 0x1p60f;
+    out[DL_MAX_FAMILIES] = fminf(fmaxf(qv, coarse), 0x1p60f);
   }
+}
+
+// One block over every item (the batched form runs one such block per member).
+__device__ void qscale_body(const dl_grad_args& A, float* out) {
+  __shared__ float sh[1024];
+  float bk[DL_MAX_FAMILIES], bg;
+  qscale_items(A, 0, A.J, bk, bg, sh);
+  if (threadIdx.x == 0) qscale_finish(A, bk, bg, out);
+}
+
+// Many blocks, one item per thread: each wavefront reduces its lanes' bounds with
+// shuffles and folds them into five device words with integer atomic max (the
+// bounds are >= 0, so their bit patterns order like the values); the last
+// wavefront to arrive (an arrival counter) reads the words, writes the scales
+// and clears the words and the counter for the next launch.  No wavefront waits.
+constexpr int DL_QS_ITEMS = 256;
+constexpr int DL_QS_VALS = DL_MAX_FAMILIES + 1;
+__global__ void __launch_bounds__(DL_QS_ITEMS) qscale_multi(dl_grad_args A, float* out, unsigned* words,
+                                                            unsigned* cnt) {
+  float bk[DL_MAX_FAMILIES] = {0.f, 0.f, 0.f, 0.f};
+  float bg = 0.f;
+  const int j = (int)(blockIdx.x * DL_QS_ITEMS + threadIdx.x);
+  if (j < A.J) qscale_item(A, j, A.glob ? A.mu[(size_t)A.m * A.J] : 0.f, bk, bg);
+  float v[DL_QS_VALS] = {bk[0], bk[1], bk[2], bk[3], bg};
+#pragma unroll
+  for (int k = 0; k < DL_QS_VALS; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] = fmaxf(v[k], __shfl_xor(v[k], o, 64));
+  if ((threadIdx.x & 63) != 0) return;
+#pragma unroll
+  for (int k = 0; k < DL_QS_VALS; ++k)
+    if (v[k] > 0.f) atomicMax(words + k, __float_as_uint(v[k]));
+  __threadfence();  // the maxima before the arrival
+  const unsigned waves = gridDim.x * (DL_QS_ITEMS / 64);
+  if (atomicAdd(cnt, 1u) != waves - 1) return;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < DL_QS_VALS; ++k) v[k] = __uint_as_float(atomicExch(words + k, 0u));
+  const float fb[DL_MAX_FAMILIES] = {v[0], v[1], v[2], v[3]};
+  qscale_finish(A, fb, v[4], out);
+  atomicExch(cnt, 0u);  // ready for the next launch
 }
 
 __global__ void __launch_bounds__(1024) qscale_kernel(dl_grad_args A, float* out) { qscale_body(A, out); }
@@ -151,7 +198,13 @@ __global__ void __launch_bounds__(1024) qscale_batch_kernel(const dl_grad_args* 
 
 dl_status dl_launch_qscale(const dl_problem* P, const float* mu, double gamma) {
   dl_grad_args A = dl_make_grad_args(P, mu, gamma);
-  hipLaunchKernelGGL(qscale_kernel, dim3(1), dim3(1024), 0, P->stream, A, P->qs_dev);
+  const int nb = (P->J + DL_QS_ITEMS - 1) / DL_QS_ITEMS;
+  if (nb <= 1) {
+    hipLaunchKernelGGL(qscale_kernel, dim3(1), dim3(1024), 0, P->stream, A, P->qs_dev);
+  } else {
+    hipLaunchKernelGGL(qscale_multi, dim3(nb), dim3(DL_QS_ITEMS), 0, P->stream, A, P->qs_dev, P->qs_words,
+                       P->qs_cnt);
+  }
   DL_HIP_TRY(hipGetLastError());
   return DL_OK;
 }

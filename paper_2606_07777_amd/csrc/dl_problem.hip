@@ -165,7 +165,7 @@ void free_problem(dl_problem* P) {
   if (!P) return;
   void* ptrs[] = {P->rp, P->idx, P->cval, P->aval, P->orig_rp, P->wg_task, P->wg_clock, P->b, P->D, P->part, P->acc,
                   P->obj_part, P->pobj_part, P->mu, P->rfac, P->lam_tmp, P->cert_out, P->ext, P->qs_dev,
-                  P->upd_flag};
+                  P->qs_words, P->qs_cnt, P->upd_flag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->cert_host) (void)hipHostFree(P->cert_host);
@@ -483,6 +483,10 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   DL_TRY(dmalloc(P, &P->cert_out, 16));
   DL_HIP_TRY(hipHostMalloc((void**)&P->cert_host, sizeof(double) * 16, hipHostMallocDefault));
   DL_TRY(dmalloc(P, &P->qs_dev, (size_t)DL_MAX_FAMILIES + 4));
+  DL_TRY(dmalloc(P, &P->qs_words, (size_t)DL_MAX_FAMILIES + 1));
+  DL_TRY(dmalloc(P, &P->qs_cnt, 1));
+  DL_HIP_TRY(hipMemsetAsync(P->qs_words, 0, sizeof(unsigned) * (DL_MAX_FAMILIES + 1), st));
+  DL_HIP_TRY(hipMemsetAsync(P->qs_cnt, 0, sizeof(unsigned), st));
   DL_TRY(dmalloc(P, &P->upd_flag, 1));
   {
     // the families' coarsest scales, then the global-count row's (x <= radius per element)
