@@ -136,10 +136,19 @@ __device__ __forceinline__ void hist_add(unsigned long long* h, int rb, float w,
     atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(h) + rb), (unsigned long long)(long long)q);
 }
 
-// w >= 0 (families with a == 1): rounds half up with one fused multiply-add and
-// a truncating convert; the 64-bit addend has a zero high word.
+// FP32 to u32, truncating, with the hardware convert's saturation: negative
+// values (and -inf) give 0.
+__device__ __forceinline__ uint32_t cvt_u32_sat(float f) {
+  uint32_t q;
+  asm("v_cvt_u32_f32 %0, %1" : "=v"(q) : "v"(f));
+  return q;
+}
+
+// Families with a == 1: adds x = max(w, 0), rounded half up on the grid, with one
+// fused multiply-add and a saturating convert (w <= 0 adds nothing, as x = 0
+// would); the 64-bit addend has a zero high word.
 __device__ __forceinline__ void hist_add_pos(unsigned long long* h, int rb, float w, float qs) {
-  const uint32_t q = __float2uint_rz(fmaf(w, qs, 0.5f));
+  const uint32_t q = cvt_u32_sat(fmaf(w, qs, 0.5f));
   if (q != 0) atomicAdd(reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(h) + rb), (unsigned long long)q);
 }
 
@@ -218,6 +227,16 @@ struct RowRegs {
 template <int MF, bool HAS_A, int KMAX>
 __device__ __forceinline__ int item_off(const RowRegs<MF, HAS_A, KMAX>& R, int k) {
   return (k & 1) ? (int)(R.jp[k >> 1] >> 16) : (int)(R.jp[k >> 1] & 0xFFFFu);
+}
+
+// Histogram byte offset (2 jb) of the item in slot k.  The low half-word is
+// taken with a byte permute, so the offset is one permute and one shift-add with
+// the histogram's base (an and-mask here becomes shift, mask and add).
+template <int MF, bool HAS_A, int KMAX>
+__device__ __forceinline__ int hist_off(const RowRegs<MF, HAS_A, KMAX>& R, int k) {
+  const uint32_t w = R.jp[k >> 1];
+  const uint32_t jb = (k & 1) ? (w >> 16) : __builtin_amdgcn_perm(0u, w, 0x0c0c0100u);
+  return (int)(jb << 1);
 }
 
 // Which row element a lane's register slot k holds.  The G lanes of a group
@@ -327,10 +346,13 @@ __device__ __forceinline__ void load_rows(const dl_grad_args& A, const TaskMeta&
   }
 }
 
-// v = (c + sum_k a_k mu_k[j]) * (-1/gamma) in place of c; -inf outside the row.
-// Slot k is inside the row when 0 <= slot_off(k, lid) - shift < d; with lo =
-// shift - 4 lid (wide) or -lid, that is the one unsigned compare
-// (c_k - lo) < d on the compile-time part c_k of the slot's offset.
+// v = (c + sum_k a_k mu_k[j]) * (-1/gamma) in place of c, computed as
+// c (-1/gamma) + sum_k a_k mu'_k[j] from the staged mu' = mu (-1/gamma); -inf
+// outside the row.  Slot k is inside the row when 0 <= slot_off(k, lid) - shift
+// < d; with lo = shift - 4 lid that is lo <= c_k < d + lo on the compile-time
+// part c_k = slot_off(k, 0) of the slot's offset.  lo <= 3 <= c_k for k >= 3,
+// so those slots test the upper end only; slots 0..2 take the one unsigned
+// compare (c_k - lo) < d.
 template <int GLOG, int MF, bool HAS_A, int KMAX, typename TV, int MODE>
 __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& m, int K, int lid,
                                          RowRegs<MF, HAS_A, KMAX>& R, const float* s_mu,
@@ -338,6 +360,7 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
   K = __builtin_amdgcn_readfirstlane(K);
   const unsigned d = (unsigned)(m.e - m.s);
   const int lo = row_shift(m) - slot_off<GLOG>(0, lid);
+  const int hi = (int)d + lo;
   const int mm = A.m;
   if constexpr ((MODE & M_VIN) == 0) {
     unpack_rows<TV, KMAX>(R.c, K);
@@ -355,7 +378,7 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
   }
   DL_FOR_KC(k, KMAX, K) {
     {
-      const bool in = (unsigned)(slot_off<GLOG>(k, 0) - lo) < d;
+      const bool in = k < 3 ? (unsigned)(slot_off<GLOG>(k, 0) - lo) < d : slot_off<GLOG>(k, 0) < hi;
       float val;
       if constexpr ((MODE & M_VIN) != 0) {
         val = R.c[k];
@@ -382,7 +405,7 @@ __device__ __forceinline__ void gather_v(const dl_grad_args& A, const TaskMeta& 
           sdot = f < mm ? t : sdot;
         }
         if constexpr ((MODE & M_REPAIR) != 0) cc[k] = R.c[k];
-        val = (R.c[k] + sdot) * A.neg_inv_gamma;  // eq. 3 argument
+        val = fmaf(R.c[k], A.neg_inv_gamma, sdot);  // eq. 3 argument
       }
       R.c[k] = in ? val : -INFINITY;
     }
@@ -487,34 +510,39 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   if (boxcut) {
     theta = boxcut_theta<GLOG, KMAX, HAS_A>(v, K, z, A.upper);
   } else if (!box) {
-    // pass A: largest two entries, positive part and its count
-    float m1 = -INFINITY, m2 = -INFINITY, sp = 0.f;
-    unsigned cpi = 0;  // integer count: one compare and one add-with-carry per element
-    DL_FOR_KC(k, KMAX, K) {
-      {
-        m2 = __builtin_amdgcn_fmed3f(m1, m2, v[k]);  // second largest of {m1 >= m2, v}
-        m1 = fmaxf(m1, v[k]);
-        sp += fmaxf(v[k], 0.f);
-        cpi += v[k] > 0.f;
-      }
-    }
-    gtop2<GLOG>(m1, m2);
+    // pass A: the positive part's sum.  Where it fits (the inequality form), x = v+
+    // and the row needs nothing more; no user here (d = 0) needs nothing either.
+    float sp = 0.f;
+    DL_FOR_KC(k, KMAX, K) sp += fmaxf(v[k], 0.f);
     sp = gsum<GLOG>(sp);
-    const float cp = gsum<GLOG>((float)cpi);
     const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
-    bool done;
-    if (m1 == -INFINITY || (!eq && sp <= z)) {
-      done = true;                       // no user here, or the positive part already fits
-    } else if (m1 - m2 >= z) {
-      theta = m1 - z;                    // the leader alone carries mass z
-      done = true;
-    } else {
-      // start left of the root, as close as the pass's sums allow: the root is at least
-      // (sum of any k entries - z) / k, here for k = 1 (the leader), k = 2 (the two
-      // leaders, both above that value since m1 - m2 < z) and k = #positive
-      theta = fmaxf(m1 - z, 0.5f * (m1 + m2 - z));
-      if (sp > z) theta = fmaxf(theta, (sp - z) * __builtin_amdgcn_rcpf(cp));  // Newton step from 0
-      done = false;
+    bool done = !(m.e > m.s) || (!eq && sp <= z);
+    if (__any(!done)) {
+      // pass B, only in wavefronts with a row left: largest two entries and the
+      // positive count (an integer: one compare and one add-with-carry per element)
+      float m1 = -INFINITY, m2 = -INFINITY;
+      unsigned cpi = 0;
+      DL_FOR_KC(k, KMAX, K) {
+        {
+          m2 = __builtin_amdgcn_fmed3f(m1, m2, v[k]);  // second largest of {m1 >= m2, v}
+          m1 = fmaxf(m1, v[k]);
+          cpi += v[k] > 0.f;
+        }
+      }
+      gtop2<GLOG>(m1, m2);
+      const float cp = gsum<GLOG>((float)cpi);
+      if (!done) {
+        if (m1 - m2 >= z) {
+          theta = m1 - z;  // the leader alone carries mass z
+          done = true;
+        } else {
+          // start left of the root, as close as the sums allow: the root is at least
+          // (sum of any k entries - z) / k, here for k = 1 (the leader), k = 2 (the
+          // two leaders, both above that value since m1 - m2 < z) and k = #positive
+          theta = fmaxf(m1 - z, 0.5f * (m1 + m2 - z));
+          if (sp > z) theta = fmaxf(theta, (sp - z) * __builtin_amdgcn_rcpf(cp));  // Newton step from 0
+        }
+      }
     }
     for (int it = 0; it < 64 && __any(!done); ++it) {
       float f = 0.f, mina = INFINITY;
@@ -542,8 +570,13 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   }
 
   float lobj = 0.f;
-  auto emit = [&](int k, float x) {
+  // t is the element's value before the clamp at 0: x = max(t, 0).  The
+  // histogram of a family with a == 1 and the global count convert t itself
+  // with a saturating convert, which maps t <= 0 to 0 as x would.
+  auto emit = [&](int k, float t) {
     {
+      const float x = fmaxf(t, 0.f);
+      (void)x;  // unused in the histogram-only modes of families with a == 1
       if constexpr ((MODE & M_XOUT) != 0) {
         const int p = slot_off<GLOG>(k, lid) - row_shift(m);
         if (p >= 0 && p < (int)(m.e - m.s)) A.x_out[m.os + p] = x;
@@ -552,15 +585,13 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
 #pragma unroll
         for (int f = 0; f < MF; ++f) {
           if (f < A.m) {
-            float w = x;
-            if constexpr (HAS_A) {
-              if (A.a_slot[f] >= 0) w = R.a[f][k] * x;
-            }
-            hist_put<HAS_A, MODE>(s_hist, f * 8 * A.J + 2 * item_off(R, k), w, qs[f], A);
+            float w = t;
+            if constexpr (HAS_A) w = A.a_slot[f] >= 0 ? R.a[f][k] * x : x;
+            hist_put<HAS_A, MODE>(s_hist, f * 8 * A.J + hist_off(R, k), w, qs[f], A);
           }
         }
         // global-count row: x >= 0 on its own grid, summed per lane in 64 bits
-        if constexpr ((MODE & M_GLOB) != 0) acc.gcnt += __float2uint_rz(fmaf(x, qs[DL_MAX_FAMILIES], 0.5f));
+        if constexpr ((MODE & M_GLOB) != 0) acc.gcnt += cvt_u32_sat(fmaf(t, qs[DL_MAX_FAMILIES], 0.5f));
       }
       if constexpr ((MODE & M_OBJ) != 0) {
         // (c + A^T lam) x + gamma/2 x^2, with c + A^T lam = -gamma v; 0 when x = 0
@@ -577,12 +608,12 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   };
   // one loop per projection kind, so the kind is not re-tested per element
   if (box) {
-    DL_FOR_KC(k, KMAX, K) emit(k, fminf(fmaxf(v[k], 0.f), z));
+    DL_FOR_KC(k, KMAX, K) emit(k, fminf(v[k], z));
   } else if (boxcut) {
     const float u = A.upper;
-    DL_FOR_KC(k, KMAX, K) emit(k, fminf(fmaxf(v[k] - theta, 0.f), u));
+    DL_FOR_KC(k, KMAX, K) emit(k, fminf(v[k] - theta, u));
   } else {
-    DL_FOR_KC(k, KMAX, K) emit(k, fmaxf(v[k] - theta, 0.f));
+    DL_FOR_KC(k, KMAX, K) emit(k, v[k] - theta);
   }
   if (MODE & (M_OBJ | M_REPAIR)) acc.obj += (double)lobj;
 }
@@ -678,7 +709,7 @@ __device__ __forceinline__ float long_v(const dl_grad_args& A, const float* s_mu
       sdot = fmaf(a, lds_word(s_mu, f * 4 * A.J + j), sdot);
     }
   }
-  return (c + sdot) * A.neg_inv_gamma;
+  return fmaf(c, A.neg_inv_gamma, sdot);  // the staged duals carry -1/gamma
 }
 
 template <int MF, bool HAS_A, typename TV, int MODE>
@@ -839,9 +870,12 @@ __device__ __forceinline__ void grad_body(const dl_grad_args& A, int64_t w0, int
   unsigned long long t_start = 0;
   if (A.wg_clock && tid == 0) t_start = (unsigned long long)wall_clock64();
   if (need_mu) {
-    // family 0's words carry the global-count dual as well when its a == 1
+    // family 0's words carry the global-count dual as well when its a == 1; every
+    // word is staged times -1/gamma, so v = c (-1/gamma) + sum_k a_k mu'_k[j] is one
+    // fused multiply-add per element past the coupling sum
     const float mug0 = (A.glob && A.a_slot[0] < 0) ? A.mu[mJ] : 0.f;
-    for (int r = tid; r < mu_n; r += DL_WG) s_mu[r] = r < A.J ? A.mu[r] + mug0 : A.mu[r];
+    const float ng = A.neg_inv_gamma;
+    for (int r = tid; r < mu_n; r += DL_WG) s_mu[r] = (r < A.J ? A.mu[r] + mug0 : A.mu[r]) * ng;
   }
   for (int r = tid; r < rf_n; r += DL_WG) s_rf[r] = A.rfac[r];
   for (int r = tid; r < hist_n; r += DL_WG) s_hist[r] = 0ull;
