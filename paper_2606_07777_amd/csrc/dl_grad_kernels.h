@@ -100,6 +100,26 @@ __device__ __forceinline__ void top2_step(float& m1, float& m2) {
   m2 = fmaxf(lo, fmaxf(m2, o2));
   m1 = hi;
 }
+// (largest, second, third) over the group: the k-th largest of two sorted
+// triples a, b is the largest min(a_i, b_j) over i + j = k (a_0 = b_0 = +inf)
+template <int STEP>
+__device__ __forceinline__ void top3_step(float& m1, float& m2, float& m3) {
+  const float o1 = xstep<STEP>(m1), o2 = xstep<STEP>(m2), o3 = xstep<STEP>(m3);
+  const float n3 = fmaxf(fmaxf(m3, o3), fmaxf(fminf(m1, o2), fminf(m2, o1)));
+  const float n2 = fmaxf(fmaxf(m2, o2), fminf(m1, o1));
+  m1 = fmaxf(m1, o1);
+  m2 = n2;
+  m3 = n3;
+}
+template <int GLOG>
+__device__ __forceinline__ void gtop3(float& m1, float& m2, float& m3) {
+  if constexpr (GLOG > 0) top3_step<0>(m1, m2, m3);
+  if constexpr (GLOG > 1) top3_step<1>(m1, m2, m3);
+  if constexpr (GLOG > 2) top3_step<2>(m1, m2, m3);
+  if constexpr (GLOG > 3) top3_step<3>(m1, m2, m3);
+  if constexpr (GLOG > 4) top3_step<4>(m1, m2, m3);
+  if constexpr (GLOG > 5) top3_step<5>(m1, m2, m3);
+}
 template <int GLOG>
 __device__ __forceinline__ void gtop2(float& m1, float& m2) {
   if constexpr (GLOG > 0) top2_step<0>(m1, m2);
@@ -510,39 +530,45 @@ __device__ __forceinline__ void project_task(const dl_grad_args& A, const TaskMe
   if (boxcut) {
     theta = boxcut_theta<GLOG, KMAX, HAS_A>(v, K, z, A.upper);
   } else if (!box) {
-    // pass A: the positive part's sum.  Where it fits (the inequality form), x = v+
-    // and the row needs nothing more; no user here (d = 0) needs nothing either.
-    float sp = 0.f;
-    DL_FOR_KC(k, KMAX, K) sp += fmaxf(v[k], 0.f);
+    // one pass: the three largest entries and the positive part's sum.  These
+    // settle most rows without a search: no user here; the positive part fits
+    // (inequality form); the leader alone carries mass z (m1 - m2 >= z); or the two
+    // leaders do, theta = (m1 + m2 - z) / 2, when the third lies at or below it.
+    float m1 = -INFINITY, m2 = -INFINITY, m3 = -INFINITY, sp = 0.f;
+    DL_FOR_KC(k, KMAX, K) {
+      {
+        m3 = __builtin_amdgcn_fmed3f(m2, m3, v[k]);  // third largest of {m1 >= m2 >= m3, v}
+        m2 = __builtin_amdgcn_fmed3f(m1, m2, v[k]);
+        m1 = fmaxf(m1, v[k]);
+        sp += fmaxf(v[k], 0.f);
+      }
+    }
+    gtop3<GLOG>(m1, m2, m3);
     sp = gsum<GLOG>(sp);
     const bool eq = A.proj == DL_PROJ_SIMPLEX_EQ;
-    bool done = !(m.e > m.s) || (!eq && sp <= z);
+    bool done = true;
+    if (m1 == -INFINITY || (!eq && sp <= z)) {
+      // theta = 0
+    } else if (m1 - m2 >= z) {
+      theta = m1 - z;
+    } else {
+      // m2 > theta2 since m1 - m2 < z; the top two are the active set when m3 <= theta2
+      const float theta2 = 0.5f * (m1 + m2 - z);
+      theta = theta2;
+      if (!(m3 <= theta2)) {
+        // start left of the root, as close as the sums allow: the root is at least
+        // (sum of any k entries - z) / k, here for the top two and the top three
+        theta = fmaxf(theta2, (m1 + m2 + m3 - z) * (1.f / 3.f));
+        done = false;
+      }
+    }
     if (__any(!done)) {
-      // pass B, only in wavefronts with a row left: largest two entries and the
-      // positive count (an integer: one compare and one add-with-carry per element)
-      float m1 = -INFINITY, m2 = -INFINITY;
+      // only in wavefronts with a row left: the positive count (an integer: one
+      // compare and one add-with-carry per element) for the bound with k = #positive
       unsigned cpi = 0;
-      DL_FOR_KC(k, KMAX, K) {
-        {
-          m2 = __builtin_amdgcn_fmed3f(m1, m2, v[k]);  // second largest of {m1 >= m2, v}
-          m1 = fmaxf(m1, v[k]);
-          cpi += v[k] > 0.f;
-        }
-      }
-      gtop2<GLOG>(m1, m2);
+      DL_FOR_KC(k, KMAX, K) cpi += v[k] > 0.f;
       const float cp = gsum<GLOG>((float)cpi);
-      if (!done) {
-        if (m1 - m2 >= z) {
-          theta = m1 - z;  // the leader alone carries mass z
-          done = true;
-        } else {
-          // start left of the root, as close as the sums allow: the root is at least
-          // (sum of any k entries - z) / k, here for k = 1 (the leader), k = 2 (the
-          // two leaders, both above that value since m1 - m2 < z) and k = #positive
-          theta = fmaxf(m1 - z, 0.5f * (m1 + m2 - z));
-          if (sp > z) theta = fmaxf(theta, (sp - z) * __builtin_amdgcn_rcpf(cp));  // Newton step from 0
-        }
-      }
+      if (!done && sp > z) theta = fmaxf(theta, (sp - z) * __builtin_amdgcn_rcpf(cp));  // Newton step from 0
     }
     for (int it = 0; it < 64 && __any(!done); ++it) {
       float f = 0.f, mina = INFINITY;
