@@ -465,7 +465,7 @@ def main():
     ap.add_argument("--layout", default="bucketed", choices=["bucketed", "wavefront"],
                     help="user-to-lane mapping; wavefront = one wavefront per user (baseline layout)")
     ap.add_argument("--wg-per-cu", type=int, default=8, help="largest workgroups-per-CU grid the tuner may pick")
-    ap.add_argument("--tune-rounds", type=int, default=3, help="workgroup-split balancing rounds (0 = off)")
+    ap.add_argument("--tune-rounds", type=int, default=10, help="workgroup-split balancing rounds (0 = off)")
     ap.add_argument("--copy-ref-mb", type=int, default=0,
                     help="run a device copy of this size first (reference kernel for counter scaling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -336,7 +336,10 @@ typedef struct {
  * was created with), the task split is re-balanced `rounds` times from
  * measured per-workgroup times (steady-clock stamps), and the fastest grid and
  * split are kept for every later pass of this problem.  Does not change the
- * solver's iterate.  Synchronises the stream.
+ * solver's iterate.  Synchronises the stream.  A round costs three passes per
+ * grid size; each re-deal starts from one noisy measurement, so more rounds
+ * give the best-timed split more chances (10M x 10k production rows: 3 rounds
+ * leave a workgroup imbalance of 1.05-1.17, 10 rounds 1.02-1.03).
  */
 dl_status dl_solver_autotune(dl_solver* s, int32_t rounds, dl_tune_result* out);
 /*

@@ -456,7 +456,7 @@ class Solver:
         _check(load().dl_solver_certificate(self.handle, ctypes.byref(st)))
         return st.as_dict()
 
-    def autotune(self, rounds: int = 3) -> dict:
+    def autotune(self, rounds: int = 10) -> dict:
         """dl_solver_autotune: balance the workgroup split from measured times."""
         r = dl_tune_result()
         _check(load().dl_solver_autotune(self.handle, int(rounds), ctypes.byref(r)))
