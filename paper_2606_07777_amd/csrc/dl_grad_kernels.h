@@ -14,8 +14,8 @@
 // around a bucketed, fused simplex projection (Sections 4.1-4.3); here the three
 // are one streaming pass over the user-major CSR:
 //
-//  * each workgroup (1024 lanes, one per CU) stages lam (m*J FP32) in LDS once
-//    and gathers from there;
+//  * each workgroup (1024 lanes, one per CU) stages lam (m*J FP32, times
+//    -1/gamma) in LDS once and gathers from there;
 //  * users are reordered by degree, longest first, and served by groups of
 //    G = 2^glog lanes holding up to KMAX elements each in registers; G is a
 //    compile-time constant per degree bucket so every load of a row uses an
@@ -24,11 +24,14 @@
 //    a wavefront-wide loop over the row;
 //  * each wavefront prefetches the next task's row pointers and row data while
 //    it computes the current task (software pipelining);
-//  * the simplex threshold: the paper's early exit when the positive part
-//    already fits, an exact exit when the largest entry leads the second by at
-//    least z, otherwise Newton steps from below on f(theta) = sum max(v-theta,0)
-//    - z (each step is the exact threshold of the current active set; the pass
-//    that forms it also checks whether the set survives the step);
+//  * the simplex threshold: one pass keeps the three largest entries and the
+//    positive sum; then the paper's early exit when the positive part already
+//    fits, an exact exit when the largest entry leads the second by at least z,
+//    an exact exit when the two largest carry z with the third at or below
+//    their threshold, otherwise Newton steps from below on f(theta) =
+//    sum max(v-theta,0) - z (each step is the exact threshold of the current
+//    active set; the pass that forms it also checks whether the set survives
+//    the step);
 //  * a_k * x is rounded to a per-family fixed-point grid and added with 64-bit
 //    integer LDS atomics into a per-workgroup histogram over items; integer
 //    addition is associative, so the sums are bitwise reproducible for any

@@ -206,16 +206,19 @@ def _ladder_instance(wl, proj, radius=1.0, upper=0.0, seed=0):
 
 
 def _adversarial_v(inst, z, seed):
-    """Per row, one of eight patterns (by row index): ties (constant rows, both
+    """Per row, one of ten patterns (by row index): ties (constant rows, both
     fitting and not fitting), a positive part summing to z exactly, a leader
-    exactly z above the second entry (the top-2 exit boundary), all entries <= 0,
-    magnitudes spread over 1e-6 .. 1e6, many ties at the threshold, plain normal."""
+    exactly z above the second entry (the one-leader exit boundary), all entries
+    <= 0, magnitudes spread over 1e-6 .. 1e6, many ties at the threshold, plain
+    normal, a third entry exactly at the two leaders' threshold (the two-leader
+    exit boundary, z = 1), and three leaders over a tail of ties just below
+    their threshold (the Newton path, z = 1)."""
     rng = np.random.default_rng(seed)
     v = np.empty(inst.nnz, dtype=np.float32)
     for i in range(inst.n_users):
         s, e = int(inst.row_ptr[i]), int(inst.row_ptr[i + 1])
         d = e - s
-        kind = i % 8
+        kind = i % 10
         if kind == 0:
             r = np.full(d, np.float32(2.0 * z / d + 0.125))        # constant, sum > z
         elif kind == 1:
@@ -246,6 +249,14 @@ def _adversarial_v(inst, z, seed):
         elif kind == 6:
             r = np.full(d, 0.75)                                   # ties at the threshold plus a tail
             r[: max(1, d // 3)] = 1.5
+        elif kind == 8:
+            r = rng.uniform(-1.0, 0.2, size=d)                     # m3 = (m1 + m2 - z) / 2 exactly
+            r[:3] = [1.0, 0.5, 0.25][:d]
+            rng.shuffle(r)
+        elif kind == 9:
+            r = np.full(d, 0.40625)                                # ties just below (m1+m2+m3-z)/3
+            r[:3] = [1.0, 0.75, 0.5][:d]
+            rng.shuffle(r)
         else:
             r = rng.normal(size=d) * 2
         v[s:e] = r
@@ -269,8 +280,8 @@ def test_project_adversarial_rows(dl, orc, wl, proj):
     vmax = np.maximum.reduceat(np.abs(v.astype(np.float64)), inst.row_ptr[:-1])
     tol = 32 * U32 * np.maximum(np.repeat(vmax, inst.degrees()), 1.0)
     err = np.abs(x - xo)
-    kinds = np.repeat(np.arange(inst.n_users) % 8, inst.degrees())
-    for kd in range(8):
+    kinds = np.repeat(np.arange(inst.n_users) % 10, inst.degrees())
+    for kd in range(10):
         m = kinds == kd
         print(f"{proj} pattern {kd}: max err {err[m].max():.2e}, worst err/tol {(err[m] / tol[m]).max():.3f}")
     assert np.all(err <= tol), float((err / tol).max())
