@@ -55,7 +55,8 @@ constexpr int DL_MAX_ITEMS = 16383;
 constexpr size_t DL_LDS_BYTES = 160 * 1024;
 constexpr int DL_MAX_FAMILIES = 4;
 static_assert(4 * DL_MAX_ITEMS <= 0xFFFF, "item byte offsets 4 j are stored in 16 bits");
-// Elements per lane in the group path: families with a == 1 only, and with a stored.
+// Elements per lane in the group path: the one-family kernel (a stored or not),
+// and the multi-family kernels, whose coefficient registers need the room.
 #ifndef DL_KMAX_PLAIN
 #define DL_KMAX_PLAIN 12
 #endif

@@ -16,7 +16,7 @@
 namespace {
 constexpr int GV_MF = DL_GV_MF;
 constexpr bool GV_A = DL_GV_A != 0;
-constexpr int GV_KMAX = GV_A ? DL_KMAX_A : DL_KMAX_PLAIN;
+constexpr int GV_KMAX = (GV_A && GV_MF > 1) ? DL_KMAX_A : DL_KMAX_PLAIN;
 using GV_TV = std::conditional_t<DL_GV_BF16 != 0, uint16_t, float>;
 }  // namespace
 

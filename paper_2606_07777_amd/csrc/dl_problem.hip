@@ -278,7 +278,7 @@ dl_status create_impl(const dl_problem_desc* d, dl_problem* P) {
   }
   // kernel variant by family count: one family (unless windowed), two, or up to four
   P->mf = (m == 1 && P->tile_rows == 0) ? 1 : (m <= 2 ? 2 : 4);
-  P->kmax = (P->mf == 1 && !P->has_a) ? DL_KMAX_PLAIN : DL_KMAX_A;
+  P->kmax = (P->mf == 1) ? DL_KMAX_PLAIN : DL_KMAX_A;
   const int kmax = P->kmax;
   DL_CHECK_ARG(d->layout == DL_LAYOUT_BUCKETED || d->layout == DL_LAYOUT_WAVEFRONT, "unknown layout");
   const bool wavefront = d->layout == DL_LAYOUT_WAVEFRONT;
